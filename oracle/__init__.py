@@ -1,0 +1,153 @@
+"""FP64 CPU oracle of the lattice Boltzmann step for the Bona-Masso system.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark import this package.  It is a plain, slow,
+scalar C implementation (``lbref.c``) written from the paper, sharing no code
+with the GPU library; this module only marshals arguments through ctypes.
+
+Arrays: u is float64 (16, nz, ny, nx); f is float64 (16, 19, nz, ny, nx),
+the distributions at the current time (after streaming).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+HARMONIC = 0
+GEODESIC = 1
+NF = 16
+NQ = 19
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        build()
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.lbref_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_int, ctypes.POINTER(P)]
+    lib.lbref_create.restype = ctypes.c_int
+    lib.lbref_destroy.argtypes = [P]
+    lib.lbref_destroy.restype = None
+    lib.lbref_init_fields.argtypes = [P, dp]
+    lib.lbref_step.argtypes = [P, ctypes.c_longlong]
+    lib.lbref_moments.argtypes = [P, dp]
+    lib.lbref_get_distributions.argtypes = [P, dp]
+    lib.lbref_set_distributions.argtypes = [P, dp]
+    lib.lbref_nsteps_done.argtypes = [P]
+    lib.lbref_nsteps_done.restype = ctypes.c_longlong
+    lib.lbref_lattice_d3q19.argtypes = [ctypes.POINTER(ctypes.c_int), dp]
+    lib.lbref_lattice_d3q19.restype = None
+    lib.lbref_point_rhs.argtypes = [dp, ctypes.c_int, dp]
+    lib.lbref_point_feq.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+    lib.lbref_point_feq.restype = None
+    lib.lbref_num_threads.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+class Oracle:
+    """One periodic lattice evolved by the CPU oracle."""
+
+    def __init__(self, nx: int, ny: int, nz: int, tau: float, slicing: int = HARMONIC):
+        lib = _load()
+        self._lib = lib
+        self.shape = (nz, ny, nx)
+        self.nsite = nx * ny * nz
+        h = ctypes.c_void_p()
+        _check(lib.lbref_create(nx, ny, nz, float(tau), int(slicing), ctypes.byref(h)), "create")
+        self._h = h
+
+    def close(self) -> None:
+        if self._h:
+            self._lib.lbref_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_fields(self, u0: np.ndarray) -> None:
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        assert u0.shape == (NF,) + self.shape, u0.shape
+        _check(self._lib.lbref_init_fields(self._h, _dp(u0)), "init_fields")
+
+    def step(self, n: int = 1) -> None:
+        _check(self._lib.lbref_step(self._h, int(n)), "step")
+
+    def moments(self) -> np.ndarray:
+        out = np.empty((NF,) + self.shape, dtype=np.float64)
+        _check(self._lib.lbref_moments(self._h, _dp(out)), "moments")
+        return out
+
+    def distributions(self) -> np.ndarray:
+        out = np.empty((NF, NQ) + self.shape, dtype=np.float64)
+        _check(self._lib.lbref_get_distributions(self._h, _dp(out)), "get_distributions")
+        return out
+
+    def set_distributions(self, f: np.ndarray) -> None:
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (NF, NQ) + self.shape
+        _check(self._lib.lbref_set_distributions(self._h, _dp(f)), "set_distributions")
+
+    @property
+    def steps_done(self) -> int:
+        return int(self._lib.lbref_nsteps_done(self._h))
+
+
+def lattice_d3q19():
+    lib = _load()
+    c = (ctypes.c_int * 57)()
+    w = np.empty(19, dtype=np.float64)
+    lib.lbref_lattice_d3q19(c, _dp(w))
+    return np.array(list(c), dtype=np.int64).reshape(19, 3), w
+
+
+def point_rhs(alpha, g6, K6, V, A, D18, slicing: int = HARMONIC) -> dict:
+    """Right-hand sides and flux of the Bona-Masso system at one point."""
+    lib = _load()
+    inp = np.concatenate([[alpha], g6, K6, V, A, D18]).astype(np.float64)
+    assert inp.shape == (37,)
+    out = np.empty(34, dtype=np.float64)
+    _check(lib.lbref_point_rhs(_dp(inp), int(slicing), _dp(out)), "point_rhs")
+    return {
+        "R_alpha": out[0],
+        "R_gamma": out[1:7].copy(),
+        "R_K": out[7:13].copy(),
+        "Omega": out[13:16].copy(),
+        "lambda": out[16:34].reshape(3, 6).copy(),
+    }
+
+
+def point_feq(kind: int, u: float, F=(0.0, 0.0, 0.0)) -> np.ndarray:
+    lib = _load()
+    Fa = np.asarray(F, dtype=np.float64)
+    out = np.empty(19, dtype=np.float64)
+    lib.lbref_point_feq(int(kind), float(u), _dp(Fa), _dp(out))
+    return out
+
+
+def num_threads() -> int:
+    return int(_load().lbref_num_threads())

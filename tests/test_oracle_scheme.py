@@ -1,0 +1,221 @@
+"""Pins of the oracle's time step as a whole.
+
+- Minkowski is a fixed point (to the rounding of the weights).
+- Budget: streaming conserves, the collision adds exactly R (sum over
+  directions of the source distributions plus the half-source shift).
+- Conservation of every distribution sum when all sources vanish.
+- Plane symmetry: a wave along x on N x M x L equals the N x 1 x 1 run bit for
+  bit; the (1,1,0) wave on N x N x L equals N x N x 1; an axis permutation
+  permutes the fields.
+- A hand-expanded single step (lapse perturbation, geodesic slicing) against
+  exact rational arithmetic: the D3Q19 step reduces to a D1Q3 average for the
+  lapse and a central difference of the flux for K_xx.
+- Linearised dynamics against the Chapman-Enskog closed form: the resolved
+  gauge-wave mode grows at (tau - 1/2) kappa^2 / 6 per step and travels at
+  light speed 1.
+- The paper's gauge-wave life-time (about 2e3 steps until the error exceeds
+  10 %) at its own setup, and first-order convergence at constant numerical
+  diffusivity (section "Relaxation Time and Numerical Diffusivity").
+"""
+
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _run(u0, tau, steps, slicing=oracle.HARMONIC):
+    nz, ny, nx = u0.shape[1:]
+    o = oracle.Oracle(nx, ny, nz, tau, slicing)
+    o.init_fields(u0)
+    o.step(steps)
+    return o
+
+
+def test_minkowski_fixed_point():
+    """Flat space at rest is a fixed point.  The rounded weights sum to 1 + 2^-52
+    in double precision, so it holds to that rounding level, without drift."""
+    u0 = workloads.minkowski(5, 4, 3)
+    o = oracle.Oracle(5, 4, 3, 0.6)
+    o.init_fields(u0)
+    f0 = o.distributions()
+    o.step(500)
+    assert np.abs(o.distributions() - f0).max() <= 1e-17
+    assert np.abs(o.moments() - u0).max() <= 2.3e-16
+    assert np.array_equal(o.moments()[7:], u0[7:])  # K and V stay exactly zero
+
+
+@pytest.mark.parametrize("slicing", [oracle.HARMONIC, oracle.GEODESIC])
+def test_budget_identity(slicing):
+    """sum_x sum_q f(n+1) = sum_x (ubar + R)(n) = sum_x (2 u(n) - ubar(n))."""
+    u0 = workloads.random_state(6, 5, 4, seed=3, amp=0.05)
+    o = oracle.Oracle(6, 5, 4, 0.7, slicing)
+    o.init_fields(u0)
+    o.step(2)
+    u = o.moments()
+    ubar = o.distributions().sum(axis=1)
+    o.step(1)
+    after = o.distributions().sum(axis=(1, 2, 3, 4))
+    expect = (2.0 * u - ubar).sum(axis=(1, 2, 3))
+    assert np.allclose(after, expect, rtol=0, atol=1e-12)
+
+
+def test_conservation_without_sources():
+    """Lapse perturbation with geodesic slicing, K = V = 0, gamma = delta: every
+    right-hand side is zero at t = 0, so the first step conserves each field's
+    distribution sum."""
+    rng = np.random.default_rng(7)
+    u0 = workloads.minkowski(7, 6, 5)
+    u0[0] += 0.01 * rng.uniform(-1, 1, size=u0[0].shape)
+    o = oracle.Oracle(7, 6, 5, 0.9, oracle.GEODESIC)
+    o.init_fields(u0)
+    s0 = o.distributions().sum(axis=(1, 2, 3, 4))
+    o.step(1)
+    s1 = o.distributions().sum(axis=(1, 2, 3, 4))
+    assert np.allclose(s1, s0, rtol=0, atol=1e-12)
+
+
+def test_x_wave_plane_symmetry_bitwise():
+    u3 = workloads.gauge_wave_x(12, 5, 4, 0.1, 12)
+    u1 = workloads.gauge_wave_x(12, 1, 1, 0.1, 12)
+    f3 = _run(u3, 0.8, 20).distributions()
+    f1 = _run(u1, 0.8, 20).distributions()
+    for z in range(4):
+        for y in range(5):
+            assert np.array_equal(f3[:, :, z, y, :], f1[:, :, 0, 0, :])
+
+
+def test_diagonal_wave_z_invariance_bitwise():
+    u3 = workloads.gauge_wave_diag(8, 5, 0.1)
+    u1 = workloads.gauge_wave_diag(8, 1, 0.1)
+    f3 = _run(u3, 0.8, 15).distributions()
+    f1 = _run(u1, 0.8, 15).distributions()
+    for z in range(5):
+        assert np.array_equal(f3[:, :, z], f1[:, :, 0])
+
+
+def _swap_xy_fields(u):
+    """Relabel axes x <-> y in every tensor component."""
+    out = u.copy()
+    perm_sym = [3, 1, 4, 0, 2, 5]  # (xx,xy,xz,yy,yz,zz) -> index of the x<->y image
+    for s in range(6):
+        out[1 + perm_sym[s]] = u[1 + s]
+        out[7 + perm_sym[s]] = u[7 + s]
+    out[13], out[14] = u[14], u[13]
+    return out
+
+
+def test_axis_permutation():
+    ux = workloads.gauge_wave_x(10, 1, 1, 0.1, 10)
+    uy = _swap_xy_fields(ux).transpose(0, 1, 3, 2).copy()  # wave now along y on 1 x 10 x 1
+    mx = _run(ux, 0.8, 20).moments()
+    my = _run(uy, 0.8, 20).moments()
+    back = _swap_xy_fields(my.transpose(0, 1, 3, 2))
+    assert np.allclose(back, mx, rtol=0, atol=1e-13)
+
+
+def test_hand_expanded_step():
+    """N x 1 x 1 lattice, only the lapse perturbed (dyadic values), geodesic
+    slicing.  At t = 0 every right-hand side vanishes, f = f^eq, and the only
+    flux is F^x_xx = alpha A_x = (alpha(x+1) - alpha(x-1))/2.  One step then
+    gives, in exact arithmetic (D3Q19 collapsed onto x: weights 1/6, 2/3, 1/6):
+        sum_q f_alpha(x)  = (alpha(x-1) + 4 alpha(x) + alpha(x+1)) / 6
+        sum_q f_Kxx(x)    = (F(x-1) - F(x+1)) / 2
+        gamma stays delta, V stays 0, the other K components stay 0."""
+    N = 6
+    alpha = [Fraction(1) + Fraction(k, 64) for k in (3, -5, 7, 1, -2, 6)]
+    u0 = workloads.minkowski(N, 1, 1)
+    u0[0, 0, 0, :] = [float(a) for a in alpha]
+    o = oracle.Oracle(N, 1, 1, 0.8, oracle.GEODESIC)
+    o.init_fields(u0)
+    o.step(1)
+    m = o.distributions().sum(axis=1)[:, 0, 0, :]
+
+    def F(y):
+        return (alpha[(y + 1) % N] - alpha[(y - 1) % N]) / 2
+
+    for x in range(N):
+        ea = (alpha[(x - 1) % N] + 4 * alpha[x] + alpha[(x + 1) % N]) / 6
+        ek = (F(x - 1) - F(x + 1)) / 2
+        # lapse: 19 rounded products summed, a few units in the last place of
+        # values near 1.  K_xx: the step recomputes the flux from the summed
+        # lapse, whose rounding (2^-52) the central difference amplifies by
+        # 1/(alpha(x+1) - alpha(x-1)) ~ 10, i.e. ~1e-14 relative on F.
+        assert abs(m[0, x] - float(ea)) <= 2e-15
+        assert abs(m[7, x] - float(ek)) <= 1e-15
+    assert np.allclose(m[[1, 4, 6]], 1.0, rtol=0, atol=2e-15)
+    assert np.allclose(m[[2, 3, 5]], 0.0, rtol=0, atol=1e-18)
+    assert np.allclose(m[8:16], 0.0, rtol=0, atol=1e-17)
+
+
+def _mode(u, N):
+    x = np.arange(N)
+    return ((u[1, 0, 0, :] - 1.0) * np.exp(-2j * np.pi * x / N)).sum() * 2 / N
+
+
+@pytest.mark.parametrize("N,tau", [(100, 1.0), (200, 1.5)])
+def test_linear_growth_matches_chapman_enskog(N, tau):
+    """Chapman-Enskog on the equilibria: alpha and gamma diffuse with
+    (tau - 1/2) c_s^2, while K's flux moves at speed 1 > c_s and contributes
+    (tau - 1/2)(c_s^2 - 1); the coupled wave's amplitude changes at
+    -1/2 (tau - 1/2)(2 c_s^2 - 1) kappa^2 = (tau - 1/2) kappa^2 / 6 per step."""
+    kappa = 2 * math.pi / N
+    o = oracle.Oracle(N, 1, 1, tau)
+    o.init_fields(workloads.gauge_wave_x(N, 1, 1, 1e-8, N))
+    a0 = _mode(o.moments(), N)
+    o.step(N // 4)
+    a1 = _mode(o.moments(), N)
+    # light speed: a quarter wavelength travelled in N/4 steps
+    assert abs(np.angle(a1 / a0) + math.pi / 2) < 0.03
+    o.step(200 - N // 4)
+    a2 = _mode(o.moments(), N)
+    growth = math.log(abs(a2) / abs(a0)) / 200
+    closed = (tau - 0.5) * kappa ** 2 / 6
+    assert abs(growth / closed - 1) < 0.01, (growth, closed)
+
+
+@pytest.mark.slow
+def test_paper_gauge_wave_lifetime():
+    """Paper setup (800 sites per wavelength, tau = 4.5, A = 1e-3): the relative
+    error of gamma_xx's wave stays small for about 2e3 steps and then exceeds
+    10 % (section "Errors in the Validation Tests")."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_gauge_wave.json")))
+    N, tau, A = g["sites_per_wavelength"], g["tau_over_dt"], g["amplitude"]
+    o = oracle.Oracle(N, 1, 1, tau)
+    o.init_fields(workloads.gauge_wave_x(N, 1, 1, A, N))
+    first = None
+    for n in range(0, 3001, 100):
+        u = o.moments()
+        ua = workloads.gauge_wave_x(N, 1, 1, A, N, t=n)
+        dev = np.abs(u[1] - ua[1]).max() / np.abs(ua[1] - 1).max()
+        val = max(np.abs(u[i] - ua[i]).max() / np.abs(ua[i]).max() for i in (0, 1))
+        if first is None:
+            assert val < g["reported_accuracy_relative"]
+        if first is None and dev > 0.10:
+            first = n
+        o.step(100)
+    reported = g["reported_steps_until_relative_error_exceeds_10_percent"]
+    assert first is not None and 0.75 * reported <= first <= 1.5 * reported, first
+
+
+def test_first_order_convergence_at_constant_diffusivity():
+    """eta = (tau - 1/2) c_s^2 dx (Eq. numdifrel in physical units with dt = dx)
+    fixed at 0.0016..., error at t = 400 dt falls linearly with dx."""
+    eta = 0.005 / 3.0
+    errs = []
+    for N in (100, 200, 400):
+        tau = 0.5 + 3.0 * eta * N
+        o = _run(workloads.gauge_wave_x(N, 1, 1, 1e-3, N), tau, 400)
+        u = o.moments()
+        ua = workloads.gauge_wave_x(N, 1, 1, 1e-3, N, t=400)
+        errs.append(np.abs(u[1] - ua[1]).max() / np.abs(ua[1] - 1).max())
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(0.85 < s < 1.2 for s in slopes), slopes
