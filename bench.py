@@ -1,0 +1,175 @@
+"""Throughput of the Bona-Masso lattice Boltzmann step on one MI355X.
+
+Workload: the 256^3 periodic lattice with the gauge wave along the (1,1,0)
+diagonal, A = 0.1, tau = 0.6, harmonic slicing, FP64 storage and arithmetic
+(the north-star 3D configuration).  One "step" is one lattice Boltzmann time
+step over the whole lattice (moments, lapse/metric half source, derivative
+stencil, geometry and sources, flux, equilibria, BGK relaxation with source,
+pull streaming).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line with the throughput in field-site updates per second
+(16 fields per site), the roofline of the step against HBM bandwidth
+(algorithmic bytes: every distribution read once and written once, 16 x 19 x
+8 B each way per site), and the CPU oracle timed on a bounded sample of the
+same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu]
+"""
+
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+FIELDS, Q = 16, 19
+ALG_BYTES_PER_SITE_FP64 = 2 * FIELDS * Q * 8   # read + write every distribution once
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1505_02037_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(nsite: int):
+    """HBM bytes per step from the committed counter summary, if it was taken
+    on the current kernels (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_fp64_step.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d["bytes_per_site_per_step"] * nsite
+
+
+def cpu_baseline(n: int, tau: float, target_s: float = 15.0) -> dict:
+    """The oracle (plain FP64 C, OpenMP over sites) on a bounded sample of the
+    same workload: the (1,1,0) wave on n x n x 8 sites."""
+    import oracle
+    import workloads
+
+    nz = 8
+    u0 = workloads.gauge_wave_diag(n, nz, 0.1)
+    o = oracle.Oracle(n, n, nz, tau)
+    o.init_fields(u0)
+    t0 = time.perf_counter()
+    o.step(1)
+    dt1 = time.perf_counter() - t0
+    steps = max(1, min(200, int(target_s / max(dt1, 1e-6))))
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    sites = n * n * nz
+    return {
+        "value": FIELDS * sites * steps / dt,
+        "unit": "field-site updates/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"(1,1,0) gauge wave A=0.1 tau={tau} on {n}x{n}x{nz} sites, {steps} steps, {dt:.1f} s",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--tau", type=float, default=0.6)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is described in the design notes, not built)"}))
+        return 2
+
+    import torch
+
+    import workloads
+    from paper_1505_02037_amd import lb
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 2
+    torch.cuda.set_device(0)
+    n, tau = args.n, args.tau
+    nsite = n * n * n
+    stream = torch.cuda.Stream()
+    g = lb.Lattice(n, n, n, tau, device=0, stream=stream.cuda_stream)
+    with torch.cuda.stream(stream):
+        u0 = torch.from_numpy(workloads.gauge_wave_diag(n, 1, 0.1)).cuda().expand(16, n, n, n).contiguous()
+    stream.synchronize()
+    g.init_fields(u0)
+    del u0
+    g.step(args.warmup)
+    stream.synchronize()
+
+    g.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(args.steps)          # timed with HIP events per kernel on the handle's stream
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ktimes = g.kernel_times()
+    g.close()
+
+    ms_step = 1000.0 * wall / args.steps
+    value = FIELDS * nsite * args.steps / wall
+    step_kernel_ms = sum(ktimes.values())
+    alg_bytes = ALG_BYTES_PER_SITE_FP64 * nsite
+    achieved = alg_bytes / (step_kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(nsite)
+    line = {
+        "metric": "field-site updates/s",
+        "value": value,
+        "unit": "field-site updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3D gauge wave along (1,1,0), {n}^3 periodic, A=0.1, tau={tau}, harmonic slicing, "
+                        "FP64 distributions, D3Q19, 16 Bona-Masso fields",
+            "lattice": [n, n, n],
+            "tau": tau,
+            "form": "fp64",
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "+".join(ktimes.keys()),
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_step": alg_bytes,
+            "kernel_ms": ktimes,
+        },
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(64, tau)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,120 @@
+/*
+ * lb.h -- C-ABI of the MI355X (gfx950) lattice Boltzmann step for the
+ * Bona-Masso flux-conservative Einstein system (Ilseven & Mendoza,
+ * "Lattice Boltzmann Model for Numerical Relativity").
+ *
+ * The library evolves the 16 fields u = (alpha, gamma_ij, K_ij, V_k) of the
+ * Bona-Masso system (section "Bona-Masso evolution equations", vacuum, zero
+ * shift) with one distribution per field on the D3Q19 velocity set (section
+ * "Lattice Boltzmann Model"), BGK collision with a source term (Eq. numlb),
+ * the per-field equilibria and sources (Eqs. alfa .. ekstsor) and the
+ * half-source macroscopic moments, on a periodic lattice (section "Gauge
+ * choices").  Lattice units: dt = dx = 1.
+ *
+ * Conventions shared by every entry point
+ *   fields   0 alpha | 1..6 gamma (xx,xy,xz,yy,yz,zz) | 7..12 K (same order)
+ *            | 13..15 V (x,y,z)
+ *   u arrays double, [16][nz][ny][nx], x fastest, no padding.
+ *   f arrays double, [16][19][nz][ny][nx], the distributions at the current
+ *            time after streaming, D3Q19 directions in the paper's order.
+ *   pointers "on_device" = 1: a device pointer on the handle's device (the
+ *            call is stream-ordered on the handle's stream); 0: host memory
+ *            (the call copies synchronously).  The caller owns every array it
+ *            passes; the library copies what it needs and keeps no pointer.
+ *   errors   every int-returning function returns LB_OK (0) or a negative
+ *            LB_E* code; lb_strerror names it.  A failed call leaves the
+ *            handle usable unless it returns LB_EDEVICE.
+ *   threads  one handle is driven from one host thread at a time.
+ */
+#ifndef LBNR_LB_H
+#define LBNR_LB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_OK 0
+#define LB_EINVAL (-1)    /* bad argument or configuration */
+#define LB_ENOMEM (-2)    /* device or host allocation failed */
+#define LB_EDEVICE (-3)   /* a HIP call failed (message in lb_last_error) */
+#define LB_ESTATE (-4)    /* handle not initialised with lb_init_fields */
+
+#define LB_D3Q19 19
+
+#define LB_SLICING_HARMONIC 0 /* Q = tr K  (harmonic slicing)  */
+#define LB_SLICING_GEODESIC 1 /* Q = 0     (geodesic slicing)  */
+
+#define LB_FP64 0      /* distributions stored and collided in FP64 */
+#define LB_FP32_DEV 1  /* distributions stored as FP32 deviations from the
+                          rest-state equilibrium (reserved) */
+
+typedef struct lb_handle lb_handle; /* opaque, owned by the library */
+
+typedef struct lb_config {
+    int lattice;     /* LB_D3Q19 */
+    int nx, ny, nz;  /* periodic extents, each >= 1 */
+    double tau;      /* relaxation time in units of dt (Eq. lbe); > 1/2 */
+    int slicing;     /* LB_SLICING_HARMONIC or LB_SLICING_GEODESIC */
+    int precision;   /* LB_FP64 */
+    int device;      /* HIP device ordinal, or -1 for the current device */
+    void *stream;    /* hipStream_t to run on, or NULL: the library creates
+                        and owns a stream of default priority */
+} lb_config;
+
+/* Allocates two distribution buffers and per-site scratch on the device.
+ * Fails with LB_EINVAL on a bad config, LB_ENOMEM if the device memory is
+ * not available.  *out is set to NULL on failure. */
+int lb_create(const lb_config *cfg, lb_handle **out);
+
+/* Device bytes lb_create would allocate for cfg (0 on a bad config). */
+size_t lb_device_bytes(const lb_config *cfg);
+
+/* Initial distributions from the fields u0 ([16][nz][ny][nx]):
+ * f_q = f^eq_q(u0) - w_q R(u0)/2 with every quantity (right-hand sides R,
+ * derivatives of the lapse and metric, flux) evaluated at u0, so that the
+ * half-source moments at t = 0 return u0 up to O(dt^2).  Resets the step
+ * counter. */
+int lb_init_fields(lb_handle *h, const double *u0, int on_device);
+
+/* Enqueues nsteps time steps on the handle's stream; does not synchronise.
+ * nsteps >= 0. */
+int lb_step(lb_handle *h, long long nsteps);
+
+/* Macroscopic fields u = sum_q f_q + R/2 at the current time into u_out
+ * ([16][nz][ny][nx]).  Synchronises the handle's stream. */
+int lb_moments(lb_handle *h, double *u_out, int on_device);
+
+/* The distributions at the current time into f_out ([16][19][nz][ny][nx]).
+ * Synchronises the handle's stream. */
+int lb_get_distributions(lb_handle *h, double *f_out, int on_device);
+
+/* Error norms of the current fields against u_ref ([16][nz][ny][nx]),
+ * computed on the device in FP64.  Per field F (arrays of 16):
+ *   max_abs[F] = max_x |u_F - ref_F|,  l2[F] = sqrt(sum_x (u_F - ref_F)^2 / N),
+ *   ref_max[F] = max_x |ref_F|.
+ * Any output pointer may be NULL.  Synchronises the handle's stream. */
+int lb_error_norms(lb_handle *h, const double *u_ref, int on_device,
+                   double *max_abs, double *l2, double *ref_max);
+
+/* Steps taken since lb_init_fields. */
+long long lb_steps_done(const lb_handle *h);
+
+/* Average device time in milliseconds of each kernel of the last lb_step
+ * call that ran with timing enabled (lb_set_timing), measured with HIP
+ * events on the handle's stream.  names[i] and ms[i] for i < *count (at most
+ * cap entries).  Returns LB_ESTATE if no timed call has run. */
+int lb_set_timing(lb_handle *h, int enable);
+int lb_kernel_times(lb_handle *h, const char **names, double *ms, int cap, int *count);
+
+void lb_destroy(lb_handle *h);
+
+const char *lb_strerror(int code);
+/* Text of the last HIP failure seen by this thread (empty if none). */
+const char *lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBNR_LB_H */

@@ -1,0 +1,347 @@
+// lb_api.hip -- the C-ABI declared in include/lb.h (host side).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/lb.h"
+#include "lb_kernels.h"
+
+using lbnr::Geom;
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+int fail_hip(hipError_t e, const char *what)
+{
+    snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
+    return LB_EDEVICE;
+}
+
+#define LB_HIP(call)                                         \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return fail_hip(e_, #call);    \
+    } while (0)
+
+// Keeps the caller's current device and restores it on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = (dev < 0 || dev == prev) || hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
+
+} // namespace
+
+struct lb_handle {
+    lb_config cfg;
+    Geom G;
+    int device = -1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    double *fbuf[2] = {nullptr, nullptr}; // distribution buffers [16][19][ps]
+    double *ubar = nullptr;               // [16][ps]
+    double *lm = nullptr;                 // [7][ps]
+    int cur = 0;                          // buffer holding the current state
+    bool initialised = false;
+    long long steps = 0;
+    double omega = 0.0, srcfac = 0.0;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    double ms_moments = 0.0, ms_collide = 0.0;
+    long long timed_launches = 0;
+};
+
+namespace {
+
+int validate(const lb_config *c)
+{
+    if (!c) return LB_EINVAL;
+    if (c->lattice != LB_D3Q19) return LB_EINVAL;
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1) return LB_EINVAL;
+    const double n = (double)c->nx * (double)c->ny * (double)c->nz;
+    if (n > 4294967295.0) return LB_EINVAL; // 32-bit site indices
+    if (!(c->tau > 0.5) || !isfinite(c->tau)) return LB_EINVAL;
+    if (c->slicing != LB_SLICING_HARMONIC && c->slicing != LB_SLICING_GEODESIC) return LB_EINVAL;
+    if (c->precision != LB_FP64) return LB_EINVAL;
+    return LB_OK;
+}
+
+Geom geom_of(const lb_config *c)
+{
+    Geom G;
+    G.nx = c->nx;
+    G.ny = c->ny;
+    G.nz = c->nz;
+    G.nsite = (uint32_t)((size_t)c->nx * c->ny * c->nz);
+    G.ps = round_up(G.nsite, 64);
+    return G;
+}
+
+size_t dist_bytes(const Geom &G) { return (size_t)16 * 19 * G.ps * sizeof(double); }
+
+// the buffer not holding the current state: free scratch between steps
+double *spare(lb_handle *h) { return h->fbuf[h->cur ^ 1]; }
+
+void free_all(lb_handle *h)
+{
+    for (int i = 0; i < 2; ++i)
+        if (h->fbuf[i]) (void)hipFree(h->fbuf[i]);
+    if (h->ubar) (void)hipFree(h->ubar);
+    if (h->lm) (void)hipFree(h->lm);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+}
+
+int ensure_events(lb_handle *h, size_t n)
+{
+    while (h->events.size() < n) {
+        hipEvent_t e;
+        LB_HIP(hipEventCreate(&e));
+        h->events.push_back(e);
+    }
+    return LB_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+size_t lb_device_bytes(const lb_config *cfg)
+{
+    if (validate(cfg) != LB_OK) return 0;
+    const Geom G = geom_of(cfg);
+    return 2 * dist_bytes(G) + (size_t)(16 + 7) * G.ps * sizeof(double);
+}
+
+int lb_create(const lb_config *cfg, lb_handle **out)
+{
+    if (!out) return LB_EINVAL;
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc != LB_OK) return rc;
+    DeviceGuard dg(cfg->device);
+    if (!dg.ok) return fail_hip(hipErrorInvalidDevice, "hipSetDevice");
+    lb_handle *h = new (std::nothrow) lb_handle();
+    if (!h) return LB_ENOMEM;
+    h->cfg = *cfg;
+    h->G = geom_of(cfg);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail_hip(hipErrorInvalidDevice, "hipGetDevice");
+    }
+    h->omega = 1.0 / cfg->tau;
+    h->srcfac = 1.0 - 0.5 * h->omega; // (1 - dt / (2 tau))
+    const Geom &G = h->G;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc((void **)&h->fbuf[i], dist_bytes(G));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->ubar, (size_t)16 * G.ps * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->lm, (size_t)7 * G.ps * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_all(h);
+        delete h;
+        snprintf(g_last_error, sizeof g_last_error, "hipMalloc: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE;
+    }
+    if (cfg->stream) {
+        h->stream = (hipStream_t)cfg->stream;
+    } else {
+        e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            free_all(h);
+            delete h;
+            return fail_hip(e, "hipStreamCreateWithFlags");
+        }
+        h->own_stream = true;
+    }
+    *out = h;
+    return LB_OK;
+}
+
+void lb_destroy(lb_handle *h)
+{
+    if (!h) return;
+    DeviceGuard dg(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    free_all(h);
+    delete h;
+}
+
+int lb_init_fields(lb_handle *h, const double *u0, int on_device)
+{
+    if (!h || !u0) return LB_EINVAL;
+    DeviceGuard dg(h->device);
+    const Geom &G = h->G;
+    const size_t ubytes = (size_t)16 * G.nsite * sizeof(double);
+    const double *du0 = u0;
+    if (!on_device) {
+        double *stage = spare(h);
+        LB_HIP(hipMemcpyAsync(stage, u0, ubytes, hipMemcpyHostToDevice, h->stream));
+        du0 = stage;
+    }
+    LB_HIP(lbnr::launch_init(G, h->cfg.slicing == LB_SLICING_HARMONIC, du0, h->lm, h->fbuf[h->cur], h->stream));
+    if (!on_device) LB_HIP(hipStreamSynchronize(h->stream));
+    h->initialised = true;
+    h->steps = 0;
+    return LB_OK;
+}
+
+int lb_step(lb_handle *h, long long nsteps)
+{
+    if (!h || nsteps < 0) return LB_EINVAL;
+    if (!h->initialised) return LB_ESTATE;
+    if (nsteps == 0) return LB_OK;
+    DeviceGuard dg(h->device);
+    const Geom &G = h->G;
+    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    if (h->timing) {
+        int rc = ensure_events(h, (size_t)2 * nsteps + 1);
+        if (rc != LB_OK) return rc;
+        LB_HIP(hipEventRecord(h->events[0], h->stream));
+    }
+    for (long long s = 0; s < nsteps; ++s) {
+        const double *fin = h->fbuf[h->cur];
+        double *fout = h->fbuf[h->cur ^ 1];
+        LB_HIP(lbnr::launch_moments(fin, G, harmonic, h->ubar, h->lm, h->stream));
+        if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 1], h->stream));
+        LB_HIP(lbnr::launch_collide(fin, fout, G, harmonic, h->omega, h->srcfac, h->ubar, h->lm, h->stream));
+        if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 2], h->stream));
+        h->cur ^= 1;
+        h->steps++;
+    }
+    if (h->timing) {
+        LB_HIP(hipStreamSynchronize(h->stream));
+        double tm = 0.0, tc = 0.0;
+        for (long long s = 0; s < nsteps; ++s) {
+            float a = 0.f, b = 0.f;
+            LB_HIP(hipEventElapsedTime(&a, h->events[2 * s], h->events[2 * s + 1]));
+            LB_HIP(hipEventElapsedTime(&b, h->events[2 * s + 1], h->events[2 * s + 2]));
+            tm += a;
+            tc += b;
+        }
+        h->ms_moments = tm / (double)nsteps;
+        h->ms_collide = tc / (double)nsteps;
+        h->timed_launches = nsteps;
+    }
+    return LB_OK;
+}
+
+int lb_moments(lb_handle *h, double *u_out, int on_device)
+{
+    if (!h || !u_out) return LB_EINVAL;
+    if (!h->initialised) return LB_ESTATE;
+    DeviceGuard dg(h->device);
+    const Geom &G = h->G;
+    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    double *dst = on_device ? u_out : spare(h);
+    LB_HIP(lbnr::launch_moments(h->fbuf[h->cur], G, harmonic, h->ubar, h->lm, h->stream));
+    LB_HIP(lbnr::launch_output(G, harmonic, h->ubar, h->lm, dst, h->stream));
+    if (!on_device)
+        LB_HIP(hipMemcpyAsync(u_out, dst, (size_t)16 * G.nsite * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    LB_HIP(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_get_distributions(lb_handle *h, double *f_out, int on_device)
+{
+    if (!h || !f_out) return LB_EINVAL;
+    if (!h->initialised) return LB_ESTATE;
+    DeviceGuard dg(h->device);
+    const Geom &G = h->G;
+    double *dst = on_device ? f_out : spare(h);
+    LB_HIP(lbnr::launch_gather(h->fbuf[h->cur], G, dst, h->stream));
+    if (!on_device)
+        LB_HIP(hipMemcpyAsync(f_out, dst, (size_t)16 * 19 * G.nsite * sizeof(double), hipMemcpyDeviceToHost,
+                              h->stream));
+    LB_HIP(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_error_norms(lb_handle *h, const double *u_ref, int on_device, double *max_abs, double *l2, double *ref_max)
+{
+    if (!h || !u_ref) return LB_EINVAL;
+    if (!h->initialised) return LB_ESTATE;
+    DeviceGuard dg(h->device);
+    const Geom &G = h->G;
+    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    // spare buffer layout: [u 16 x nsite][ref 16 x nsite][norm scratch]
+    double *u = spare(h);
+    double *ref = u + (size_t)16 * G.nsite;
+    double *scratch = ref + (size_t)16 * G.nsite;
+    LB_HIP(lbnr::launch_moments(h->fbuf[h->cur], G, harmonic, h->ubar, h->lm, h->stream));
+    LB_HIP(lbnr::launch_output(G, harmonic, h->ubar, h->lm, u, h->stream));
+    const double *dref = u_ref;
+    if (!on_device) {
+        LB_HIP(hipMemcpyAsync(ref, u_ref, (size_t)16 * G.nsite * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        dref = ref;
+    }
+    LB_HIP(lbnr::launch_norms(G, u, dref, scratch, h->stream));
+    const size_t nb = (G.nsite + 255) / 256;
+    double res[16 * 3];
+    LB_HIP(hipMemcpyAsync(res, scratch + nb * 16 * 3, sizeof res, hipMemcpyDeviceToHost, h->stream));
+    LB_HIP(hipStreamSynchronize(h->stream));
+    for (int F = 0; F < 16; ++F) {
+        if (max_abs) max_abs[F] = res[F * 3 + 0];
+        if (l2) l2[F] = res[F * 3 + 1];
+        if (ref_max) ref_max[F] = res[F * 3 + 2];
+    }
+    return LB_OK;
+}
+
+long long lb_steps_done(const lb_handle *h) { return h ? h->steps : -1; }
+
+int lb_set_timing(lb_handle *h, int enable)
+{
+    if (!h) return LB_EINVAL;
+    h->timing = enable != 0;
+    return LB_OK;
+}
+
+int lb_kernel_times(lb_handle *h, const char **names, double *ms, int cap, int *count)
+{
+    if (!h || !count) return LB_EINVAL;
+    if (h->timed_launches == 0) return LB_ESTATE;
+    static const char *kNames[2] = {"lbnr::k_moments", "lbnr::k_collide"};
+    const double vals[2] = {h->ms_moments, h->ms_collide};
+    int n = 0;
+    for (int i = 0; i < 2 && i < cap; ++i, ++n) {
+        if (names) names[i] = kNames[i];
+        if (ms) ms[i] = vals[i];
+    }
+    *count = n;
+    return LB_OK;
+}
+
+const char *lb_strerror(int code)
+{
+    switch (code) {
+    case LB_OK: return "ok";
+    case LB_EINVAL: return "invalid argument";
+    case LB_ENOMEM: return "out of device memory";
+    case LB_EDEVICE: return "HIP runtime error";
+    case LB_ESTATE: return "handle not initialised";
+    default: return "unknown error";
+    }
+}
+
+const char *lb_last_error(void) { return g_last_error; }
+
+} // extern "C"

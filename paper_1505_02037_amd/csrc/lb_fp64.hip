@@ -1,0 +1,428 @@
+// lb_fp64.hip -- FP64 kernels of the Bona-Masso lattice Boltzmann step.
+//
+// Storage (pull scheme).  A distribution buffer holds the post-collision
+// values f*_{F,q}(x) of the previous step, SoA [field][q][plane], one plane of
+// `ps` doubles per (field, direction) with x fastest (ps = nsite rounded up to
+// 64 elements, so every plane starts 512-byte aligned).  The distribution at
+// the current time is f_{F,q}(x) = buf[F][q][x - c_q] (periodic wrap).
+//
+// One time step is two launches:
+//   k_moments  pulls all 16 fields at a site, sums the moments, applies the
+//              local half-source correction of lapse and metric and writes
+//              ubar[16] and the corrected lapse/metric lm[7] per site;
+//   k_collide  reads ubar and lm at the site and lm at the six face
+//              neighbours (A_k, D_kij by central differences), evaluates S_ij,
+//              Omega_k and the flux, then pulls every distribution again,
+//              relaxes it towards its equilibrium with the source added and
+//              stores it at x in the other buffer.
+#include <hip/hip_runtime.h>
+
+#include "lb_device.h"
+#include "lb_kernels.h"
+
+namespace lbnr {
+
+struct Site {
+    int x, y, z;
+    uint32_t s;                // site index
+    uint32_t src[kQ];          // index of x - c_q (periodic)
+};
+
+__device__ __forceinline__ bool site_of(const Geom &G, uint32_t s, Site &o)
+{
+    if (s >= G.nsite) return false;
+    o.s = s;
+    o.x = (int)(s % (uint32_t)G.nx);
+    const uint32_t r = s / (uint32_t)G.nx;
+    o.y = (int)(r % (uint32_t)G.ny);
+    o.z = (int)(r / (uint32_t)G.ny);
+    return true;
+}
+
+// index of the site at (x + dx, y + dy, z + dz), periodic, |d| <= 1
+__device__ __forceinline__ uint32_t neighbour(const Geom &G, int x, int y, int z, int dx, int dy, int dz)
+{
+    int xx = x + dx, yy = y + dy, zz = z + dz;
+    xx = xx < 0 ? xx + G.nx : (xx >= G.nx ? xx - G.nx : xx);
+    yy = yy < 0 ? yy + G.ny : (yy >= G.ny ? yy - G.ny : yy);
+    zz = zz < 0 ? zz + G.nz : (zz >= G.nz ? zz - G.nz : zz);
+    return ((uint32_t)zz * (uint32_t)G.ny + (uint32_t)yy) * (uint32_t)G.nx + (uint32_t)xx;
+}
+
+__device__ __forceinline__ void pull_sources(const Geom &G, Site &o)
+{
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) o.src[q] = neighbour(G, o.x, o.y, o.z, -cx(q), -cy(q), -cz(q));
+}
+
+__device__ __forceinline__ const double *plane(const double *buf, const Geom &G, int F, int q)
+{
+    return buf + ((size_t)F * kQ + (size_t)q) * G.ps;
+}
+__device__ __forceinline__ double *plane(double *buf, const Geom &G, int F, int q)
+{
+    return buf + ((size_t)F * kQ + (size_t)q) * G.ps;
+}
+
+// ---------------------------------------------------------------------------
+// k_moments: zeroth moments of all fields and the corrected lapse/metric
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_moments(const double *__restrict__ fin, Geom G, int harmonic,
+                                                 double *__restrict__ ubar, double *__restrict__ lm)
+{
+    Site o;
+    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    pull_sources(G, o);
+    double ub[kFields];
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) s += plane(fin, G, F, q)[o.src[q]];
+        ub[F] = s;
+    }
+    double c[7], R[7];
+    lapse_metric(ub, harmonic != 0, c, R);
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) ubar[(size_t)F * G.ps + o.s] = ub[F];
+#pragma unroll
+    for (int F = 0; F < 7; ++F) lm[(size_t)F * G.ps + o.s] = c[F];
+}
+
+// A_k and D_kij at a site from the corrected lapse/metric of its neighbours
+__device__ __forceinline__ void stencil(const Geom &G, const Site &o, const double *__restrict__ lm,
+                                        double alpha, double A[3], double D[18])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t sp = neighbour(G, o.x, o.y, o.z, k == 0, k == 1, k == 2);
+        const uint32_t sm = neighbour(G, o.x, o.y, o.z, -(k == 0), -(k == 1), -(k == 2));
+        A[k] = (lm[sp] - lm[sm]) / (2.0 * alpha);
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const double *g = lm + (size_t)(1 + p) * G.ps;
+            D[k * 6 + p] = (g[sp] - g[sm]) * 0.25;
+        }
+    }
+}
+
+// Per-site collision parameters: corrected fields u[16], right-hand sides
+// R[16] and the K flux F[18], from the raw moments and the lapse/metric field.
+struct Params {
+    double u[kFields];
+    double R[kFields];
+    double F[18];
+};
+
+__device__ __forceinline__ void site_params(const Geom &G, const Site &o, int harmonic,
+                                            const double ub[kFields], const double *__restrict__ lm,
+                                            Params &P)
+{
+    double c[7], Rag[7];
+    lapse_metric(ub, harmonic != 0, c, Rag);
+#pragma unroll
+    for (int F = 0; F < 7; ++F) {
+        P.u[F] = c[F];
+        P.R[F] = Rag[F];
+    }
+    const double alpha = c[0];
+    double A[3], D[18], gi[6], S[6], Om[3], V[3];
+    stencil(G, o, lm, alpha, A, D);
+    sym_inverse(c + 1, gi);
+    bm_sources(alpha, c + 1, gi, ub + 7, ub + 13, A, D, S, Om);
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const double RK = alpha * S[p];
+        P.R[7 + p] = RK;
+        P.u[7 + p] = ub[7 + p] + 0.5 * RK;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        P.R[13 + k] = Om[k];
+        V[k] = ub[13 + k] + 0.5 * Om[k];
+        P.u[13 + k] = V[k];
+    }
+    bm_flux(alpha, c + 1, gi, V, A, D, P.F);
+}
+
+// relax one field's 19 distributions and store them at x
+template <int Fld>
+__device__ __forceinline__ void collide_field(const double *__restrict__ fin, double *__restrict__ fout,
+                                              const Geom &G, const Site &o, const Params &P,
+                                              double omega, double srcfac)
+{
+    const double u = P.u[Fld];
+    const double hR = srcfac * P.R[Fld];
+    constexpr bool isK = (Fld >= 7 && Fld <= 12);
+    constexpr int pk = isK ? Fld - 7 : 0;
+    double fl[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) fl[q] = plane(fin, G, Fld, q)[o.src[q]];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        double feq;
+        if constexpr (isK) {
+            double cF;
+            switch (q) {
+#define LBNR_CASE(Q_) case Q_: cF = cdot<Q_>(P.F[pk], P.F[6 + pk], P.F[12 + pk]); break;
+                LBNR_CASE(0) LBNR_CASE(1) LBNR_CASE(2) LBNR_CASE(3) LBNR_CASE(4) LBNR_CASE(5)
+                LBNR_CASE(6) LBNR_CASE(7) LBNR_CASE(8) LBNR_CASE(9) LBNR_CASE(10) LBNR_CASE(11)
+                LBNR_CASE(12) LBNR_CASE(13) LBNR_CASE(14) LBNR_CASE(15) LBNR_CASE(16) LBNR_CASE(17)
+                LBNR_CASE(18)
+#undef LBNR_CASE
+            default: cF = 0.0;
+            }
+            feq = wq(q) * (u + 3.0 * cF);
+        } else {
+            feq = wq(q) * u;
+        }
+        const double f = fl[q];
+        plane(fout, G, Fld, q)[o.s] = f - omega * (f - feq) + wq(q) * hR;
+    }
+}
+
+template <int Fld>
+__device__ __forceinline__ void collide_all(const double *__restrict__ fin, double *__restrict__ fout,
+                                            const Geom &G, const Site &o, const Params &P,
+                                            double omega, double srcfac)
+{
+    collide_field<Fld>(fin, fout, G, o, P, omega, srcfac);
+    if constexpr (Fld + 1 < kFields) collide_all<Fld + 1>(fin, fout, G, o, P, omega, srcfac);
+}
+
+// ---------------------------------------------------------------------------
+// k_collide: sources, flux, BGK relaxation with source, pull streaming
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_collide(const double *__restrict__ fin, double *__restrict__ fout,
+                                                 Geom G, int harmonic, double omega, double srcfac,
+                                                 const double *__restrict__ ubar, const double *__restrict__ lm)
+{
+    Site o;
+    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    double ub[kFields];
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) ub[F] = ubar[(size_t)F * G.ps + o.s];
+    Params P;
+    site_params(G, o, harmonic, ub, lm, P);
+    pull_sources(G, o);
+    collide_all<0>(fin, fout, G, o, P, omega, srcfac);
+}
+
+// ---------------------------------------------------------------------------
+// k_output: the half-source moments u = ubar + R/2 into an unpadded array
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_output(Geom G, int harmonic, const double *__restrict__ ubar,
+                                                const double *__restrict__ lm, double *__restrict__ u)
+{
+    Site o;
+    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    double ub[kFields];
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) ub[F] = ubar[(size_t)F * G.ps + o.s];
+    Params P;
+    site_params(G, o, harmonic, ub, lm, P);
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) u[(size_t)F * G.nsite + o.s] = P.u[F];
+}
+
+// ---------------------------------------------------------------------------
+// initialisation from fields u0 (unpadded): f = f^eq(u0) - w R(u0)/2, every
+// quantity at u0, stored where the first pull of each direction reads it
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_init_lm(Geom G, const double *__restrict__ u0, double *__restrict__ lm)
+{
+    Site o;
+    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+#pragma unroll
+    for (int F = 0; F < 7; ++F) lm[(size_t)F * G.ps + o.s] = u0[(size_t)F * G.nsite + o.s];
+}
+
+template <int Fld>
+__device__ __forceinline__ void init_field(double *__restrict__ fout, const Geom &G, const Site &o,
+                                           const Params &P)
+{
+    const double u = P.u[Fld];
+    const double hR = 0.5 * P.R[Fld];
+    constexpr bool isK = (Fld >= 7 && Fld <= 12);
+    constexpr int pk = isK ? Fld - 7 : 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        double feq;
+        if constexpr (isK) {
+            double cF;
+            switch (q) {
+#define LBNR_CASE(Q_) case Q_: cF = cdot<Q_>(P.F[pk], P.F[6 + pk], P.F[12 + pk]); break;
+                LBNR_CASE(0) LBNR_CASE(1) LBNR_CASE(2) LBNR_CASE(3) LBNR_CASE(4) LBNR_CASE(5)
+                LBNR_CASE(6) LBNR_CASE(7) LBNR_CASE(8) LBNR_CASE(9) LBNR_CASE(10) LBNR_CASE(11)
+                LBNR_CASE(12) LBNR_CASE(13) LBNR_CASE(14) LBNR_CASE(15) LBNR_CASE(16) LBNR_CASE(17)
+                LBNR_CASE(18)
+#undef LBNR_CASE
+            default: cF = 0.0;
+            }
+            feq = wq(q) * (u + 3.0 * cF);
+        } else {
+            feq = wq(q) * u;
+        }
+        // the pull of direction q at x reads position x - c_q
+        plane(fout, G, Fld, q)[o.src[q]] = feq - wq(q) * hR;
+    }
+    if constexpr (Fld + 1 < kFields) init_field<Fld + 1>(fout, G, o, P);
+}
+
+__global__ void __launch_bounds__(256) k_init(Geom G, int harmonic, const double *__restrict__ u0,
+                                              const double *__restrict__ lm, double *__restrict__ fout)
+{
+    Site o;
+    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    double u[kFields];
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) u[F] = u0[(size_t)F * G.nsite + o.s];
+    Params P;
+    // R_alpha, R_gamma at u0 (the corrected values are not used: u stays u0)
+    double c[7], Rag[7];
+    lapse_metric(u, harmonic != 0, c, Rag);
+    double A[3], D[18], gi[6], S[6], Om[3];
+    stencil(G, o, lm, u[0], A, D);
+    sym_inverse(u + 1, gi);
+    bm_sources(u[0], u + 1, gi, u + 7, u + 13, A, D, S, Om);
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) P.u[F] = u[F];
+#pragma unroll
+    for (int F = 0; F < 7; ++F) P.R[F] = Rag[F];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) P.R[7 + p] = u[0] * S[p];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) P.R[13 + k] = Om[k];
+    bm_flux(u[0], u + 1, gi, u + 13, A, D, P.F);
+    // the stored position of direction q is x - c_q
+    pull_sources(G, o);
+    init_field<0>(fout, G, o, P);
+}
+
+// distributions at the current time (after streaming), unpadded
+__global__ void __launch_bounds__(256) k_gather(const double *__restrict__ fin, Geom G, double *__restrict__ f)
+{
+    Site o;
+    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    pull_sources(G, o);
+#pragma unroll
+    for (int F = 0; F < kFields; ++F)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)
+            f[((size_t)F * kQ + q) * G.nsite + o.s] = plane(fin, G, F, q)[o.src[q]];
+}
+
+// ---------------------------------------------------------------------------
+// error norms: per-block partials, then one block folds them in block order
+// ---------------------------------------------------------------------------
+constexpr int kNormThreads = 256;
+
+__global__ void __launch_bounds__(kNormThreads) k_norm_partial(Geom G, const double *__restrict__ u,
+                                                               const double *__restrict__ ref,
+                                                               double *__restrict__ part)
+{
+    // part[(blockIdx.x * 16 + F) * 3 + {0: max|d|, 1: sum d^2, 2: max|ref|}]
+    __shared__ double smax[kNormThreads], ssum[kNormThreads], sref[kNormThreads];
+    const uint32_t s = blockIdx.x * kNormThreads + threadIdx.x;
+    for (int F = 0; F < kFields; ++F) {
+        double dmax = 0.0, d2 = 0.0, rmax = 0.0;
+        if (s < G.nsite) {
+            const double r = ref[(size_t)F * G.nsite + s];
+            const double d = u[(size_t)F * G.nsite + s] - r;
+            dmax = fabs(d);
+            d2 = d * d;
+            rmax = fabs(r);
+            if (d != d) dmax = d; // keep NaN visible
+        }
+        smax[threadIdx.x] = dmax;
+        ssum[threadIdx.x] = d2;
+        sref[threadIdx.x] = rmax;
+        __syncthreads();
+        for (int w = kNormThreads / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                const double a = smax[threadIdx.x], b = smax[threadIdx.x + w];
+                smax[threadIdx.x] = (a != a || b != b) ? (a + b) : fmax(a, b);
+                ssum[threadIdx.x] += ssum[threadIdx.x + w];
+                sref[threadIdx.x] = fmax(sref[threadIdx.x], sref[threadIdx.x + w]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double *p = part + ((size_t)blockIdx.x * kFields + F) * 3;
+            p[0] = smax[0];
+            p[1] = ssum[0];
+            p[2] = sref[0];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kFields) k_norm_final(const double *__restrict__ part, uint32_t nblocks,
+                                                        uint32_t nsite, double *__restrict__ out)
+{
+    const int F = threadIdx.x;
+    double dmax = 0.0, d2 = 0.0, rmax = 0.0;
+    for (uint32_t b = 0; b < nblocks; ++b) {
+        const double *p = part + ((size_t)b * kFields + F) * 3;
+        dmax = (dmax != dmax || p[0] != p[0]) ? (dmax + p[0]) : fmax(dmax, p[0]);
+        d2 += p[1];
+        rmax = fmax(rmax, p[2]);
+    }
+    out[F * 3 + 0] = dmax;
+    out[F * 3 + 1] = sqrt(d2 / (double)nsite);
+    out[F * 3 + 2] = rmax;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline dim3 grid_for(uint32_t n, int threads) { return dim3((n + threads - 1) / threads); }
+
+hipError_t launch_moments(const double *fin, const Geom &G, int harmonic, double *ubar, double *lm, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_moments, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
+    return hipGetLastError();
+}
+
+hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int harmonic, double omega,
+                          double srcfac, const double *ubar, const double *lm, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_collide, grid_for(G.nsite, 256), dim3(256), 0, st, fin, fout, G, harmonic, omega,
+                       srcfac, ubar, lm);
+    return hipGetLastError();
+}
+
+hipError_t launch_output(const Geom &G, int harmonic, const double *ubar, const double *lm, double *u, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_output, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, ubar, lm, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm, double *fout, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_lm, grid_for(G.nsite, 256), dim3(256), 0, st, G, u0, lm);
+    hipLaunchKernelGGL(k_init, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, u0, lm, fout);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const double *fin, const Geom &G, double *f, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, f);
+    return hipGetLastError();
+}
+
+size_t norm_scratch_doubles(const Geom &G)
+{
+    return (size_t)((G.nsite + kNormThreads - 1) / kNormThreads) * kFields * 3 + kFields * 3;
+}
+
+hipError_t launch_norms(const Geom &G, const double *u, const double *ref, double *scratch, hipStream_t st)
+{
+    const uint32_t nb = (G.nsite + kNormThreads - 1) / kNormThreads;
+    hipLaunchKernelGGL(k_norm_partial, dim3(nb), dim3(kNormThreads), 0, st, G, u, ref, scratch);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kFields), 0, st, scratch, nb, G.nsite,
+                       scratch + (size_t)nb * kFields * 3);
+    return hipGetLastError();
+}
+
+} // namespace lbnr

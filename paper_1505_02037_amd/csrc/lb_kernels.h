@@ -1,0 +1,27 @@
+// lb_kernels.h -- host-callable launchers of the device kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbnr {
+
+// Lattice geometry as the kernels see it.
+struct Geom {
+    int nx, ny, nz;
+    uint32_t nsite;  // nx * ny * nz
+    size_t ps;       // plane stride in elements (nsite rounded up to 64)
+};
+
+// FP64 form (lb_fp64.hip)
+hipError_t launch_moments(const double *fin, const Geom &G, int harmonic, double *ubar, double *lm, hipStream_t st);
+hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int harmonic, double omega,
+                          double srcfac, const double *ubar, const double *lm, hipStream_t st);
+hipError_t launch_output(const Geom &G, int harmonic, const double *ubar, const double *lm, double *u, hipStream_t st);
+hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm, double *fout, hipStream_t st);
+hipError_t launch_gather(const double *fin, const Geom &G, double *f, hipStream_t st);
+size_t norm_scratch_doubles(const Geom &G);
+hipError_t launch_norms(const Geom &G, const double *u, const double *ref, double *scratch, hipStream_t st);
+
+} // namespace lbnr
