@@ -19,7 +19,6 @@ same workload.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import math
@@ -35,10 +34,14 @@ FIELDS, Q = 16, 19
 ALG_BYTES_PER_SITE_FP64 = 2 * FIELDS * Q * 8   # read + write every distribution once
 
 
+STEP_SOURCES = ("lb_api.hip", "lb_device.h", "lb_fp64.hip", "lb_kernels.h")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources the timed step kernels are built from."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1505_02037_amd", "csrc", "*"))):
-        h.update(open(p, "rb").read())
+    for name in STEP_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1505_02037_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -67,7 +70,7 @@ def cpu_baseline(n: int, tau: float, target_s: float = 15.0) -> dict:
     t0 = time.perf_counter()
     o.step(1)
     dt1 = time.perf_counter() - t0
-    steps = max(1, min(200, int(target_s / max(dt1, 1e-6))))
+    steps = max(1, min(2000, int(target_s / max(dt1, 1e-6))))
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
@@ -166,7 +169,7 @@ def main() -> int:
         },
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(64, tau)
+        line["cpu_baseline"] = cpu_baseline(128, tau)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -1,0 +1,29 @@
+/*
+ * hbm_probe.h -- a plain device-to-device copy of known size.
+ *
+ * Not part of the lattice Boltzmann method: it measures the card's achievable
+ * HBM bandwidth (a copy reads and writes every byte once) and calibrates the
+ * HBM traffic counters (FETCH_SIZE / WRITE_SIZE of a copy of B bytes each
+ * way).  The roofline figures of the method's kernels are quoted against the
+ * vendor peak and against this measured ceiling.
+ */
+#ifndef LBNR_HBM_PROBE_H
+#define LBNR_HBM_PROBE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Allocates two device buffers of `bytes` each (bytes a multiple of 64) on
+ * the current device, copies src -> dst `reps` times with a streaming copy
+ * kernel (16-byte loads and stores), and returns the average milliseconds per
+ * copy in *ms (HIP events).  Returns 0, or -1 on a bad argument, -2 if the
+ * allocation fails, -3 on any other HIP error.  Frees what it allocated. */
+int hbm_copy_probe(size_t bytes, int reps, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -13,6 +13,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbnr.so")
+PROBE_LIB = os.path.join(HERE, "libhbmprobe.so")
 SOURCES = ["lb_api.hip", "lb_fp64.hip"]
 ARCH = os.environ.get("LBNR_ARCH", "gfx950")
 
@@ -31,6 +32,11 @@ def build(verbose: bool = False, extra=None) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    cmd = ["/opt/rocm/bin/hipcc", *FLAGS, os.path.join(CSRC, "hbm_probe.hip"), "-o", PROBE_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     return LIB
 
 

@@ -1,0 +1,59 @@
+// hbm_probe.hip -- streaming copy of a known size (bandwidth ceiling and
+// counter calibration; see include/hbm_probe.h).
+#include <hip/hip_runtime.h>
+
+#include "../../include/hbm_probe.h"
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+} // namespace
+
+extern "C" int hbm_copy_probe(size_t bytes, int reps, double *ms)
+{
+    if (!ms || reps < 1 || bytes == 0 || bytes % 64) return -1;
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess) return -2;
+    if (hipMalloc(&b, bytes) != hipSuccess) {
+        (void)hipFree(a);
+        return -2;
+    }
+    int rc = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const size_t n = bytes / sizeof(double2);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
+    const dim3 grid((unsigned)cus * 8), block(256);
+    float t = 0.f;
+    if (hipMemset(a, 0, bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        rc = -3;
+        goto done;
+    }
+    hipLaunchKernelGGL(k_copy, grid, block, 0, 0, (const double2 *)a, (double2 *)b, n);
+    (void)hipEventRecord(e0, 0);
+    for (int r = 0; r < reps; ++r)
+        hipLaunchKernelGGL(k_copy, grid, block, 0, 0, (const double2 *)a, (double2 *)b, n);
+    (void)hipEventRecord(e1, 0);
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = -3;
+    *ms = (double)t / reps;
+done:
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    return rc;
+}

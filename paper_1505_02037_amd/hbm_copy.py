@@ -1,0 +1,39 @@
+"""Plain device-to-device copy of a known size (include/hbm_probe.h).
+
+Two uses: the achievable-bandwidth ceiling of the card (a copy moves each byte
+once in and once out), and the calibration kernel for the HBM traffic counters
+(FETCH_SIZE / WRITE_SIZE of a copy of B bytes each way should read B).
+
+    python paper_1505_02037_amd/hbm_copy.py [--gib 4] [--reps 20]
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+
+LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhbmprobe.so")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gib", type=float, default=4.0)
+    ap.add_argument("--reps", type=int, default=20)
+    args = ap.parse_args()
+    lib = ctypes.CDLL(LIB)
+    lib.hbm_copy_probe.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    nbytes = int(args.gib * (1 << 30)) // 64 * 64
+    ms = ctypes.c_double()
+    rc = lib.hbm_copy_probe(nbytes, args.reps, ctypes.byref(ms))
+    if rc != 0:
+        print(json.dumps({"error": rc}))
+        return 1
+    print(json.dumps({"copy_bytes_each_way": nbytes, "ms_per_copy": ms.value,
+                      "GBps_read_plus_write": 2 * nbytes / (ms.value * 1e-3) / 1e9}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
