@@ -31,10 +31,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 FIELDS, Q = 16, 19
-ALG_BYTES_PER_SITE_FP64 = 2 * FIELDS * Q * 8   # read + write every distribution once
+# read + write every distribution once, per site update
+ALG_BYTES_PER_SITE = {"fp64": 2 * FIELDS * Q * 8, "fp32": 2 * FIELDS * Q * 4}
 
 
-STEP_SOURCES = ("lb_api.hip", "lb_device.h", "lb_fp64.hip", "lb_kernels.h")
+STEP_SOURCES = ("lb_api.hip", "lb_device.h", "lb_fp32.hip", "lb_fp64.hip", "lb_kernels.h", "lb_site.h")
 
 
 def kernel_source_hash() -> str:
@@ -45,10 +46,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(nsite: int):
+def measured_traffic(nsite: int, form: str):
     """HBM bytes per step from the committed counter summary, if it was taken
     on the current kernels (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic_fp64_step.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{form}_step.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -91,6 +92,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--tau", type=float, default=0.6)
+    ap.add_argument("--form", choices=("fp64", "fp32"), default="fp64",
+                    help="fp64: plain FP64 step; fp32: FP32-deviation storage and relaxation")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -110,7 +113,8 @@ def main() -> int:
     n, tau = args.n, args.tau
     nsite = n * n * n
     stream = torch.cuda.Stream()
-    g = lb.Lattice(n, n, n, tau, device=0, stream=stream.cuda_stream)
+    precision = lb.FP64 if args.form == "fp64" else lb.FP32_DEV
+    g = lb.Lattice(n, n, n, tau, precision=precision, device=0, stream=stream.cuda_stream)
     with torch.cuda.stream(stream):
         u0 = torch.from_numpy(workloads.gauge_wave_diag(n, 1, 0.1)).cuda().expand(16, n, n, n).contiguous()
     stream.synchronize()
@@ -132,9 +136,9 @@ def main() -> int:
     ms_step = 1000.0 * wall / args.steps
     value = FIELDS * nsite * args.steps / wall
     step_kernel_ms = sum(ktimes.values())
-    alg_bytes = ALG_BYTES_PER_SITE_FP64 * nsite
+    alg_bytes = ALG_BYTES_PER_SITE[args.form] * nsite
     achieved = alg_bytes / (step_kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(nsite)
+    traffic = measured_traffic(nsite, args.form)
     line = {
         "metric": "field-site updates/s",
         "value": value,
@@ -146,14 +150,16 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.form == "fp64" else "f32",
         "data": "synthetic",
         "config": {
             "workload": f"3D gauge wave along (1,1,0), {n}^3 periodic, A=0.1, tau={tau}, harmonic slicing, "
-                        "FP64 distributions, D3Q19, 16 Bona-Masso fields",
+                        + ("FP64 distributions" if args.form == "fp64" else
+                           "FP32 deviation distributions (FP64 moments/geometry)")
+                        + ", D3Q19, 16 Bona-Masso fields",
             "lattice": [n, n, n],
             "tau": tau,
-            "form": "fp64",
+            "form": args.form,
             "parallelism": "single GPU",
         },
         "roofline": {

@@ -18,9 +18,11 @@
  *   f arrays double, [16][19][nz][ny][nx], the distributions at the current
  *            time after streaming, D3Q19 directions in the paper's order.
  *   pointers "on_device" = 1: a device pointer on the handle's device (the
- *            call is stream-ordered on the handle's stream); 0: host memory
- *            (the call copies synchronously).  The caller owns every array it
- *            passes; the library copies what it needs and keeps no pointer.
+ *            call is stream-ordered on the handle's stream, which does not
+ *            wait for other streams: device inputs must be complete when the
+ *            call is made); 0: host memory (the call copies synchronously).
+ *            The caller owns every array it passes; the library copies what
+ *            it needs and keeps no pointer.
  *   errors   every int-returning function returns LB_OK (0) or a negative
  *            LB_E* code; lb_strerror names it.  A failed call leaves the
  *            handle usable unless it returns LB_EDEVICE.
@@ -47,8 +49,12 @@ extern "C" {
 #define LB_SLICING_GEODESIC 1 /* Q = 0     (geodesic slicing)  */
 
 #define LB_FP64 0      /* distributions stored and collided in FP64 */
-#define LB_FP32_DEV 1  /* distributions stored as FP32 deviations from the
-                          rest-state equilibrium (reserved) */
+#define LB_FP32_DEV 1  /* distributions stored and streamed in FP32 as
+                          deviations from the rest-state equilibrium
+                          (alpha = 1, gamma = delta, K = V = 0), relaxed in
+                          FP32; moments, the lapse/metric correction, the
+                          derivative stencil, the geometry, the sources, the
+                          flux and the error norms stay FP64 */
 
 typedef struct lb_handle lb_handle; /* opaque, owned by the library */
 
@@ -57,7 +63,7 @@ typedef struct lb_config {
     int nx, ny, nz;  /* periodic extents, each >= 1 */
     double tau;      /* relaxation time in units of dt (Eq. lbe); > 1/2 */
     int slicing;     /* LB_SLICING_HARMONIC or LB_SLICING_GEODESIC */
-    int precision;   /* LB_FP64 */
+    int precision;   /* LB_FP64 or LB_FP32_DEV */
     int device;      /* HIP device ordinal, or -1 for the current device */
     void *stream;    /* hipStream_t to run on, or NULL: the library creates
                         and owns a stream of default priority */
@@ -75,7 +81,8 @@ size_t lb_device_bytes(const lb_config *cfg);
  * f_q = f^eq_q(u0) - w_q R(u0)/2 with every quantity (right-hand sides R,
  * derivatives of the lapse and metric, flux) evaluated at u0, so that the
  * half-source moments at t = 0 return u0 up to O(dt^2).  Resets the step
- * counter. */
+ * counter.  Synchronises the handle's stream, so u0 may be released on
+ * return. */
 int lb_init_fields(lb_handle *h, const double *u0, int on_device);
 
 /* Enqueues nsteps time steps on the handle's stream; does not synchronise.

@@ -55,7 +55,7 @@ struct lb_handle {
     int device = -1;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    double *fbuf[2] = {nullptr, nullptr}; // distribution buffers [16][19][ps]
+    void *fbuf[2] = {nullptr, nullptr};   // distribution buffers [16][19][ps] (double or float)
     double *ubar = nullptr;               // [16][ps]
     double *lm = nullptr;                 // [7][ps]
     int cur = 0;                          // buffer holding the current state
@@ -80,7 +80,7 @@ int validate(const lb_config *c)
     if (n > 4294967295.0) return LB_EINVAL; // 32-bit site indices
     if (!(c->tau > 0.5) || !isfinite(c->tau)) return LB_EINVAL;
     if (c->slicing != LB_SLICING_HARMONIC && c->slicing != LB_SLICING_GEODESIC) return LB_EINVAL;
-    if (c->precision != LB_FP64) return LB_EINVAL;
+    if (c->precision != LB_FP64 && c->precision != LB_FP32_DEV) return LB_EINVAL;
     return LB_OK;
 }
 
@@ -95,10 +95,33 @@ Geom geom_of(const lb_config *c)
     return G;
 }
 
-size_t dist_bytes(const Geom &G) { return (size_t)16 * 19 * G.ps * sizeof(double); }
+size_t elem_bytes(int precision) { return precision == LB_FP32_DEV ? sizeof(float) : sizeof(double); }
+size_t dist_bytes(const Geom &G, int precision) { return (size_t)16 * 19 * G.ps * elem_bytes(precision); }
 
 // the buffer not holding the current state: free scratch between steps
-double *spare(lb_handle *h) { return h->fbuf[h->cur ^ 1]; }
+// (at least 16 x 19 x 4 bytes per site)
+double *spare(lb_handle *h) { return (double *)h->fbuf[h->cur ^ 1]; }
+
+bool fp32(const lb_handle *h) { return h->cfg.precision == LB_FP32_DEV; }
+
+// moments and corrected lapse/metric of the current state
+hipError_t run_moments(lb_handle *h)
+{
+    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    if (fp32(h))
+        return lbnr::launch_moments32((const float *)h->fbuf[h->cur], h->G, harmonic, h->ubar, h->lm, h->stream);
+    return lbnr::launch_moments((const double *)h->fbuf[h->cur], h->G, harmonic, h->ubar, h->lm, h->stream);
+}
+
+hipError_t run_collide(lb_handle *h)
+{
+    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    if (fp32(h))
+        return lbnr::launch_collide32((const float *)h->fbuf[h->cur], (float *)h->fbuf[h->cur ^ 1], h->G, harmonic,
+                                      h->omega, h->srcfac, h->ubar, h->lm, h->stream);
+    return lbnr::launch_collide((const double *)h->fbuf[h->cur], (double *)h->fbuf[h->cur ^ 1], h->G, harmonic,
+                                h->omega, h->srcfac, h->ubar, h->lm, h->stream);
+}
 
 void free_all(lb_handle *h)
 {
@@ -128,7 +151,7 @@ size_t lb_device_bytes(const lb_config *cfg)
 {
     if (validate(cfg) != LB_OK) return 0;
     const Geom G = geom_of(cfg);
-    return 2 * dist_bytes(G) + (size_t)(16 + 7) * G.ps * sizeof(double);
+    return 2 * dist_bytes(G, cfg->precision) + (size_t)(16 + 7) * G.ps * sizeof(double);
 }
 
 int lb_create(const lb_config *cfg, lb_handle **out)
@@ -151,7 +174,7 @@ int lb_create(const lb_config *cfg, lb_handle **out)
     h->srcfac = 1.0 - 0.5 * h->omega; // (1 - dt / (2 tau))
     const Geom &G = h->G;
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc((void **)&h->fbuf[i], dist_bytes(G));
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc(&h->fbuf[i], dist_bytes(G, cfg->precision));
     if (e == hipSuccess) e = hipMalloc((void **)&h->ubar, (size_t)16 * G.ps * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->lm, (size_t)7 * G.ps * sizeof(double));
     if (e != hipSuccess) {
@@ -197,8 +220,13 @@ int lb_init_fields(lb_handle *h, const double *u0, int on_device)
         LB_HIP(hipMemcpyAsync(stage, u0, ubytes, hipMemcpyHostToDevice, h->stream));
         du0 = stage;
     }
-    LB_HIP(lbnr::launch_init(G, h->cfg.slicing == LB_SLICING_HARMONIC, du0, h->lm, h->fbuf[h->cur], h->stream));
-    if (!on_device) LB_HIP(hipStreamSynchronize(h->stream));
+    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    if (fp32(h))
+        LB_HIP(lbnr::launch_init32(G, harmonic, du0, h->lm, (float *)h->fbuf[h->cur], h->stream));
+    else
+        LB_HIP(lbnr::launch_init(G, harmonic, du0, h->lm, (double *)h->fbuf[h->cur], h->stream));
+    // the caller may release u0 as soon as this returns
+    LB_HIP(hipStreamSynchronize(h->stream));
     h->initialised = true;
     h->steps = 0;
     return LB_OK;
@@ -210,19 +238,15 @@ int lb_step(lb_handle *h, long long nsteps)
     if (!h->initialised) return LB_ESTATE;
     if (nsteps == 0) return LB_OK;
     DeviceGuard dg(h->device);
-    const Geom &G = h->G;
-    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
     if (h->timing) {
         int rc = ensure_events(h, (size_t)2 * nsteps + 1);
         if (rc != LB_OK) return rc;
         LB_HIP(hipEventRecord(h->events[0], h->stream));
     }
     for (long long s = 0; s < nsteps; ++s) {
-        const double *fin = h->fbuf[h->cur];
-        double *fout = h->fbuf[h->cur ^ 1];
-        LB_HIP(lbnr::launch_moments(fin, G, harmonic, h->ubar, h->lm, h->stream));
+        LB_HIP(run_moments(h));
         if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 1], h->stream));
-        LB_HIP(lbnr::launch_collide(fin, fout, G, harmonic, h->omega, h->srcfac, h->ubar, h->lm, h->stream));
+        LB_HIP(run_collide(h));
         if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 2], h->stream));
         h->cur ^= 1;
         h->steps++;
@@ -252,7 +276,7 @@ int lb_moments(lb_handle *h, double *u_out, int on_device)
     const Geom &G = h->G;
     const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
     double *dst = on_device ? u_out : spare(h);
-    LB_HIP(lbnr::launch_moments(h->fbuf[h->cur], G, harmonic, h->ubar, h->lm, h->stream));
+    LB_HIP(run_moments(h));
     LB_HIP(lbnr::launch_output(G, harmonic, h->ubar, h->lm, dst, h->stream));
     if (!on_device)
         LB_HIP(hipMemcpyAsync(u_out, dst, (size_t)16 * G.nsite * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -266,8 +290,22 @@ int lb_get_distributions(lb_handle *h, double *f_out, int on_device)
     if (!h->initialised) return LB_ESTATE;
     DeviceGuard dg(h->device);
     const Geom &G = h->G;
+    if (fp32(h)) {
+        // one field at a time: the spare buffer holds 19 doubles per site
+        const size_t n = (size_t)19 * G.nsite;
+        for (int F = 0; F < 16; ++F) {
+            double *dst = on_device ? f_out + (size_t)F * n : spare(h);
+            LB_HIP(lbnr::launch_gather32((const float *)h->fbuf[h->cur], G, F, dst, h->stream));
+            if (!on_device)
+                LB_HIP(hipMemcpyAsync(f_out + (size_t)F * n, dst, n * sizeof(double), hipMemcpyDeviceToHost,
+                                      h->stream));
+            if (!on_device) LB_HIP(hipStreamSynchronize(h->stream));
+        }
+        LB_HIP(hipStreamSynchronize(h->stream));
+        return LB_OK;
+    }
     double *dst = on_device ? f_out : spare(h);
-    LB_HIP(lbnr::launch_gather(h->fbuf[h->cur], G, dst, h->stream));
+    LB_HIP(lbnr::launch_gather((const double *)h->fbuf[h->cur], G, dst, h->stream));
     if (!on_device)
         LB_HIP(hipMemcpyAsync(f_out, dst, (size_t)16 * 19 * G.nsite * sizeof(double), hipMemcpyDeviceToHost,
                               h->stream));
@@ -286,7 +324,7 @@ int lb_error_norms(lb_handle *h, const double *u_ref, int on_device, double *max
     double *u = spare(h);
     double *ref = u + (size_t)16 * G.nsite;
     double *scratch = ref + (size_t)16 * G.nsite;
-    LB_HIP(lbnr::launch_moments(h->fbuf[h->cur], G, harmonic, h->ubar, h->lm, h->stream));
+    LB_HIP(run_moments(h));
     LB_HIP(lbnr::launch_output(G, harmonic, h->ubar, h->lm, u, h->stream));
     const double *dref = u_ref;
     if (!on_device) {
@@ -319,7 +357,9 @@ int lb_kernel_times(lb_handle *h, const char **names, double *ms, int cap, int *
 {
     if (!h || !count) return LB_EINVAL;
     if (h->timed_launches == 0) return LB_ESTATE;
-    static const char *kNames[2] = {"lbnr::k_moments", "lbnr::k_collide"};
+    static const char *kNames64[2] = {"lbnr::k_moments", "lbnr::k_collide"};
+    static const char *kNames32[2] = {"lbnr::k_moments32", "lbnr::k_collide32"};
+    const char *const *kNames = fp32(h) ? kNames32 : kNames64;
     const double vals[2] = {h->ms_moments, h->ms_collide};
     int n = 0;
     for (int i = 0; i < 2 && i < cap; ++i, ++n) {

@@ -1,0 +1,194 @@
+// lb_fp32.hip -- FP32-deviation form of the Bona-Masso lattice Boltzmann step.
+//
+// Distributions are stored and streamed in FP32 as deviations from the
+// rest-state equilibrium, d_q = f_q - w_q u_rest (u_rest: alpha = 1,
+// gamma = delta, K = V = 0), halving the bytes per site.  The moments are
+// reconstructed in FP64 (u_rest + sum_q d_q), the lapse/metric correction, the
+// derivative stencil, the geometry, the sources and the flux stay FP64, and the
+// per-direction relaxation runs in FP32 on the deviations:
+//   d*_q = d_q - omega (d_q - d^eq_q) + w_q (1 - omega/2) R,
+//   d^eq_q = w_q (u - u_rest)                  (alpha, gamma, V)
+//          = w_q ((K - 0) + c_q . F / c_s^2)    (K).
+// Storage layout and the two-launch step are those of the FP64 form.
+#include <hip/hip_runtime.h>
+
+#include "lb_device.h"
+#include "lb_kernels.h"
+#include "lb_site.h"
+
+namespace lbnr {
+
+__host__ __device__ constexpr double urest(int F) { return (F == 0 || F == 1 || F == 4 || F == 6) ? 1.0 : 0.0; }
+__host__ __device__ constexpr float wqf(int q) { return (float)wq(q); }
+
+__global__ void __launch_bounds__(256) k_moments32(const float *__restrict__ fin, Geom G, int harmonic,
+                                                   double *__restrict__ ubar, double *__restrict__ lm)
+{
+    Site o;
+    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    pull_sources(G, o);
+    double ub[kFields];
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) s += (double)plane(fin, G, F, q)[o.src[q]];
+        ub[F] = urest(F) + s;
+    }
+    double c[7], R[7];
+    lapse_metric(ub, harmonic != 0, c, R);
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) ubar[(size_t)F * G.ps + o.s] = ub[F];
+#pragma unroll
+    for (int F = 0; F < 7; ++F) lm[(size_t)F * G.ps + o.s] = c[F];
+}
+
+template <int q>
+__device__ __forceinline__ float cdotf(float F0, float F1, float F2)
+{
+    float s = 0.0f;
+    if (cx(q) != 0) s += cx(q) > 0 ? F0 : -F0;
+    if (cy(q) != 0) s += cy(q) > 0 ? F1 : -F1;
+    if (cz(q) != 0) s += cz(q) > 0 ? F2 : -F2;
+    return s;
+}
+
+template <int Fld, int q>
+__device__ __forceinline__ void relax_one(const float *__restrict__ fin, float *__restrict__ fout, const Geom &G,
+                                          const Site &o, float om, float du, float hR, float F0, float F1,
+                                          float F2)
+{
+    constexpr bool isK = (Fld >= 7 && Fld <= 12);
+    const float d = plane(fin, G, Fld, q)[o.src[q]];
+    float deq;
+    if constexpr (isK)
+        deq = wqf(q) * (du + 3.0f * cdotf<q>(F0, F1, F2));
+    else
+        deq = wqf(q) * du;
+    plane(fout, G, Fld, q)[o.s] = d - om * (d - deq) + wqf(q) * hR;
+    if constexpr (q + 1 < kQ) relax_one<Fld, q + 1>(fin, fout, G, o, om, du, hR, F0, F1, F2);
+}
+
+template <int Fld>
+__device__ __forceinline__ void collide32_all(const float *__restrict__ fin, float *__restrict__ fout, const Geom &G,
+                                              const Site &o, const Params &P, float om, double srcfac)
+{
+    constexpr bool isK = (Fld >= 7 && Fld <= 12);
+    constexpr int pk = isK ? Fld - 7 : 0;
+    const float du = (float)(P.u[Fld] - urest(Fld));
+    const float hR = (float)(srcfac * P.R[Fld]);
+    const float F0 = isK ? (float)P.F[pk] : 0.0f;
+    const float F1 = isK ? (float)P.F[6 + pk] : 0.0f;
+    const float F2 = isK ? (float)P.F[12 + pk] : 0.0f;
+    relax_one<Fld, 0>(fin, fout, G, o, om, du, hR, F0, F1, F2);
+    if constexpr (Fld + 1 < kFields) collide32_all<Fld + 1>(fin, fout, G, o, P, om, srcfac);
+}
+
+__global__ void __launch_bounds__(256) k_collide32(const float *__restrict__ fin, float *__restrict__ fout, Geom G,
+                                                   int harmonic, double omega, double srcfac,
+                                                   const double *__restrict__ ubar, const double *__restrict__ lm)
+{
+    Site o;
+    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    double ub[kFields];
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) ub[F] = ubar[(size_t)F * G.ps + o.s];
+    Params P;
+    site_params(G, o, harmonic, ub, lm, P);
+    pull_sources(G, o);
+    collide32_all<0>(fin, fout, G, o, P, (float)omega, srcfac);
+}
+
+// initial deviations: d_q = f^eq_q(u0) - w_q R(u0)/2 - w_q u_rest (FP64, then rounded)
+template <int Fld>
+__device__ __forceinline__ void init32_field(float *__restrict__ fout, const Geom &G, const Site &o, const Params &P)
+{
+    constexpr bool isK = (Fld >= 7 && Fld <= 12);
+    constexpr int pk = isK ? Fld - 7 : 0;
+    const double du = P.u[Fld] - urest(Fld);
+    const double hR = 0.5 * P.R[Fld];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        double deq;
+        if constexpr (isK) {
+            const double cF = (double)cx(q) * P.F[pk] + (double)cy(q) * P.F[6 + pk] + (double)cz(q) * P.F[12 + pk];
+            deq = wq(q) * (du + 3.0 * cF);
+        } else {
+            deq = wq(q) * du;
+        }
+        plane(fout, G, Fld, q)[o.src[q]] = (float)(deq - wq(q) * hR);
+    }
+    if constexpr (Fld + 1 < kFields) init32_field<Fld + 1>(fout, G, o, P);
+}
+
+__global__ void __launch_bounds__(256) k_init32(Geom G, int harmonic, const double *__restrict__ u0,
+                                                const double *__restrict__ lm, float *__restrict__ fout)
+{
+    Site o;
+    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    double u[kFields];
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) u[F] = u0[(size_t)F * G.nsite + o.s];
+    Params P;
+    double c[7], Rag[7];
+    lapse_metric(u, harmonic != 0, c, Rag);
+    double A[3], D[18], gi[6], S[6], Om[3];
+    stencil(G, o, lm, u[0], A, D);
+    sym_inverse(u + 1, gi);
+    bm_sources(u[0], u + 1, gi, u + 7, u + 13, A, D, S, Om);
+#pragma unroll
+    for (int F = 0; F < kFields; ++F) P.u[F] = u[F];
+#pragma unroll
+    for (int F = 0; F < 7; ++F) P.R[F] = Rag[F];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) P.R[7 + p] = u[0] * S[p];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) P.R[13 + k] = Om[k];
+    bm_flux(u[0], u + 1, gi, u + 13, A, D, P.F);
+    pull_sources(G, o);
+    init32_field<0>(fout, G, o, P);
+}
+
+// distributions of one field at the current time, f = w u_rest + d, FP64
+__global__ void __launch_bounds__(256) k_gather32(const float *__restrict__ fin, Geom G, int F, double *__restrict__ f)
+{
+    Site o;
+    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    pull_sources(G, o);
+    const double ur = urest(F);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+        f[(size_t)q * G.nsite + o.s] = wq(q) * ur + (double)plane(fin, G, F, q)[o.src[q]];
+}
+
+static inline dim3 grid32(uint32_t n) { return dim3((n + 255) / 256); }
+
+hipError_t launch_moments32(const float *fin, const Geom &G, int harmonic, double *ubar, double *lm, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_moments32, grid32(G.nsite), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
+    return hipGetLastError();
+}
+
+hipError_t launch_collide32(const float *fin, float *fout, const Geom &G, int harmonic, double omega, double srcfac,
+                            const double *ubar, const double *lm, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_collide32, grid32(G.nsite), dim3(256), 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+                       lm);
+    return hipGetLastError();
+}
+
+hipError_t launch_init32(const Geom &G, int harmonic, const double *u0, double *lm, float *fout, hipStream_t st)
+{
+    hipError_t e = launch_copy_lm(G, u0, lm, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_init32, grid32(G.nsite), dim3(256), 0, st, G, harmonic, u0, lm, fout);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather32(const float *fin, const Geom &G, int field, double *f, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather32, grid32(G.nsite), dim3(256), 0, st, fin, G, field, f);
+    return hipGetLastError();
+}
+
+} // namespace lbnr

@@ -19,50 +19,9 @@
 
 #include "lb_device.h"
 #include "lb_kernels.h"
+#include "lb_site.h"
 
 namespace lbnr {
-
-struct Site {
-    int x, y, z;
-    uint32_t s;                // site index
-    uint32_t src[kQ];          // index of x - c_q (periodic)
-};
-
-__device__ __forceinline__ bool site_of(const Geom &G, uint32_t s, Site &o)
-{
-    if (s >= G.nsite) return false;
-    o.s = s;
-    o.x = (int)(s % (uint32_t)G.nx);
-    const uint32_t r = s / (uint32_t)G.nx;
-    o.y = (int)(r % (uint32_t)G.ny);
-    o.z = (int)(r / (uint32_t)G.ny);
-    return true;
-}
-
-// index of the site at (x + dx, y + dy, z + dz), periodic, |d| <= 1
-__device__ __forceinline__ uint32_t neighbour(const Geom &G, int x, int y, int z, int dx, int dy, int dz)
-{
-    int xx = x + dx, yy = y + dy, zz = z + dz;
-    xx = xx < 0 ? xx + G.nx : (xx >= G.nx ? xx - G.nx : xx);
-    yy = yy < 0 ? yy + G.ny : (yy >= G.ny ? yy - G.ny : yy);
-    zz = zz < 0 ? zz + G.nz : (zz >= G.nz ? zz - G.nz : zz);
-    return ((uint32_t)zz * (uint32_t)G.ny + (uint32_t)yy) * (uint32_t)G.nx + (uint32_t)xx;
-}
-
-__device__ __forceinline__ void pull_sources(const Geom &G, Site &o)
-{
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) o.src[q] = neighbour(G, o.x, o.y, o.z, -cx(q), -cy(q), -cz(q));
-}
-
-__device__ __forceinline__ const double *plane(const double *buf, const Geom &G, int F, int q)
-{
-    return buf + ((size_t)F * kQ + (size_t)q) * G.ps;
-}
-__device__ __forceinline__ double *plane(double *buf, const Geom &G, int F, int q)
-{
-    return buf + ((size_t)F * kQ + (size_t)q) * G.ps;
-}
 
 // ---------------------------------------------------------------------------
 // k_moments: zeroth moments of all fields and the corrected lapse/metric
@@ -87,62 +46,6 @@ __global__ void __launch_bounds__(256) k_moments(const double *__restrict__ fin,
     for (int F = 0; F < kFields; ++F) ubar[(size_t)F * G.ps + o.s] = ub[F];
 #pragma unroll
     for (int F = 0; F < 7; ++F) lm[(size_t)F * G.ps + o.s] = c[F];
-}
-
-// A_k and D_kij at a site from the corrected lapse/metric of its neighbours
-__device__ __forceinline__ void stencil(const Geom &G, const Site &o, const double *__restrict__ lm,
-                                        double alpha, double A[3], double D[18])
-{
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const uint32_t sp = neighbour(G, o.x, o.y, o.z, k == 0, k == 1, k == 2);
-        const uint32_t sm = neighbour(G, o.x, o.y, o.z, -(k == 0), -(k == 1), -(k == 2));
-        A[k] = (lm[sp] - lm[sm]) / (2.0 * alpha);
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            const double *g = lm + (size_t)(1 + p) * G.ps;
-            D[k * 6 + p] = (g[sp] - g[sm]) * 0.25;
-        }
-    }
-}
-
-// Per-site collision parameters: corrected fields u[16], right-hand sides
-// R[16] and the K flux F[18], from the raw moments and the lapse/metric field.
-struct Params {
-    double u[kFields];
-    double R[kFields];
-    double F[18];
-};
-
-__device__ __forceinline__ void site_params(const Geom &G, const Site &o, int harmonic,
-                                            const double ub[kFields], const double *__restrict__ lm,
-                                            Params &P)
-{
-    double c[7], Rag[7];
-    lapse_metric(ub, harmonic != 0, c, Rag);
-#pragma unroll
-    for (int F = 0; F < 7; ++F) {
-        P.u[F] = c[F];
-        P.R[F] = Rag[F];
-    }
-    const double alpha = c[0];
-    double A[3], D[18], gi[6], S[6], Om[3], V[3];
-    stencil(G, o, lm, alpha, A, D);
-    sym_inverse(c + 1, gi);
-    bm_sources(alpha, c + 1, gi, ub + 7, ub + 13, A, D, S, Om);
-#pragma unroll
-    for (int p = 0; p < 6; ++p) {
-        const double RK = alpha * S[p];
-        P.R[7 + p] = RK;
-        P.u[7 + p] = ub[7 + p] + 0.5 * RK;
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        P.R[13 + k] = Om[k];
-        V[k] = ub[13 + k] + 0.5 * Om[k];
-        P.u[13 + k] = V[k];
-    }
-    bm_flux(alpha, c + 1, gi, V, A, D, P.F);
 }
 
 // relax one field's 19 distributions and store them at x
@@ -398,9 +301,16 @@ hipError_t launch_output(const Geom &G, int harmonic, const double *ubar, const 
     return hipGetLastError();
 }
 
-hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm, double *fout, hipStream_t st)
+hipError_t launch_copy_lm(const Geom &G, const double *u0, double *lm, hipStream_t st)
 {
     hipLaunchKernelGGL(k_init_lm, grid_for(G.nsite, 256), dim3(256), 0, st, G, u0, lm);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm, double *fout, hipStream_t st)
+{
+    hipError_t e = launch_copy_lm(G, u0, lm, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_init, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, u0, lm, fout);
     return hipGetLastError();
 }

@@ -21,7 +21,15 @@ hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int ha
 hipError_t launch_output(const Geom &G, int harmonic, const double *ubar, const double *lm, double *u, hipStream_t st);
 hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm, double *fout, hipStream_t st);
 hipError_t launch_gather(const double *fin, const Geom &G, double *f, hipStream_t st);
+hipError_t launch_copy_lm(const Geom &G, const double *u0, double *lm, hipStream_t st);
 size_t norm_scratch_doubles(const Geom &G);
 hipError_t launch_norms(const Geom &G, const double *u, const double *ref, double *scratch, hipStream_t st);
+
+// FP32-deviation form (lb_fp32.hip); the output and norm kernels are shared
+hipError_t launch_moments32(const float *fin, const Geom &G, int harmonic, double *ubar, double *lm, hipStream_t st);
+hipError_t launch_collide32(const float *fin, float *fout, const Geom &G, int harmonic, double omega, double srcfac,
+                            const double *ubar, const double *lm, hipStream_t st);
+hipError_t launch_init32(const Geom &G, int harmonic, const double *u0, double *lm, float *fout, hipStream_t st);
+hipError_t launch_gather32(const float *fin, const Geom &G, int field, double *f, hipStream_t st);
 
 } // namespace lbnr

@@ -114,6 +114,10 @@ def _ptr(a, nelem: int):
     if a.dtype != torch.float64 or not a.is_contiguous() or a.numel() != nelem:
         raise ValueError("expected a contiguous float64 tensor of %d elements" % nelem)
     if a.is_cuda:
+        # The library reads and writes device arrays on the handle's stream,
+        # which does not wait for torch's: let torch's pending work on this
+        # tensor finish first.
+        torch.cuda.current_stream(a.device).synchronize()
         return ctypes.c_void_p(a.data_ptr()), 1
     return ctypes.c_void_p(a.data_ptr()), 0
 
