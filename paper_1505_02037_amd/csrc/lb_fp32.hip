@@ -15,88 +15,23 @@
 #include "lb_device.h"
 #include "lb_kernels.h"
 #include "lb_site.h"
+#include "lb_step.h"
 
 namespace lbnr {
-
-__host__ __device__ constexpr double urest(int F) { return (F == 0 || F == 1 || F == 4 || F == 6) ? 1.0 : 0.0; }
-__host__ __device__ constexpr float wqf(int q) { return (float)wq(q); }
 
 __global__ void __launch_bounds__(256) k_moments32(const float *__restrict__ fin, Geom G, int harmonic,
                                                    double *__restrict__ ubar, double *__restrict__ lm)
 {
-    Site o;
-    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
-    pull_sources(G, o);
-    double ub[kFields];
-#pragma unroll
-    for (int F = 0; F < kFields; ++F) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) s += (double)plane(fin, G, F, q)[o.src[q]];
-        ub[F] = urest(F) + s;
-    }
-    double c[7], R[7];
-    lapse_metric(ub, harmonic != 0, c, R);
-#pragma unroll
-    for (int F = 0; F < kFields; ++F) ubar[(size_t)F * G.ps + o.s] = ub[F];
-#pragma unroll
-    for (int F = 0; F < 7; ++F) lm[(size_t)F * G.ps + o.s] = c[F];
-}
-
-template <int q>
-__device__ __forceinline__ float cdotf(float F0, float F1, float F2)
-{
-    float s = 0.0f;
-    if (cx(q) != 0) s += cx(q) > 0 ? F0 : -F0;
-    if (cy(q) != 0) s += cy(q) > 0 ? F1 : -F1;
-    if (cz(q) != 0) s += cz(q) > 0 ? F2 : -F2;
-    return s;
-}
-
-template <int Fld, int q>
-__device__ __forceinline__ void relax_one(const float *__restrict__ fin, float *__restrict__ fout, const Geom &G,
-                                          const Site &o, float om, float du, float hR, float F0, float F1,
-                                          float F2)
-{
-    constexpr bool isK = (Fld >= 7 && Fld <= 12);
-    const float d = plane(fin, G, Fld, q)[o.src[q]];
-    float deq;
-    if constexpr (isK)
-        deq = wqf(q) * (du + 3.0f * cdotf<q>(F0, F1, F2));
-    else
-        deq = wqf(q) * du;
-    plane(fout, G, Fld, q)[o.s] = d - om * (d - deq) + wqf(q) * hR;
-    if constexpr (q + 1 < kQ) relax_one<Fld, q + 1>(fin, fout, G, o, om, du, hR, F0, F1, F2);
-}
-
-template <int Fld>
-__device__ __forceinline__ void collide32_all(const float *__restrict__ fin, float *__restrict__ fout, const Geom &G,
-                                              const Site &o, const Params &P, float om, double srcfac)
-{
-    constexpr bool isK = (Fld >= 7 && Fld <= 12);
-    constexpr int pk = isK ? Fld - 7 : 0;
-    const float du = (float)(P.u[Fld] - urest(Fld));
-    const float hR = (float)(srcfac * P.R[Fld]);
-    const float F0 = isK ? (float)P.F[pk] : 0.0f;
-    const float F1 = isK ? (float)P.F[6 + pk] : 0.0f;
-    const float F2 = isK ? (float)P.F[12 + pk] : 0.0f;
-    relax_one<Fld, 0>(fin, fout, G, o, om, du, hR, F0, F1, F2);
-    if constexpr (Fld + 1 < kFields) collide32_all<Fld + 1>(fin, fout, G, o, P, om, srcfac);
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < G.nsite) moments_site32(fin, G, s, harmonic, ubar, lm);
 }
 
 __global__ void __launch_bounds__(256) k_collide32(const float *__restrict__ fin, float *__restrict__ fout, Geom G,
                                                    int harmonic, double omega, double srcfac,
                                                    const double *__restrict__ ubar, const double *__restrict__ lm)
 {
-    Site o;
-    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
-    double ub[kFields];
-#pragma unroll
-    for (int F = 0; F < kFields; ++F) ub[F] = ubar[(size_t)F * G.ps + o.s];
-    Params P;
-    site_params(G, o, harmonic, ub, lm, P);
-    pull_sources(G, o);
-    collide32_all<0>(fin, fout, G, o, P, (float)omega, srcfac);
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < G.nsite) collide_site32(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm);
 }
 
 // initial deviations: d_q = f^eq_q(u0) - w_q R(u0)/2 - w_q u_rest (FP64, then rounded)

@@ -20,6 +20,7 @@
 #include "lb_device.h"
 #include "lb_kernels.h"
 #include "lb_site.h"
+#include "lb_step.h"
 
 namespace lbnr {
 
@@ -29,68 +30,8 @@ namespace lbnr {
 __global__ void __launch_bounds__(256) k_moments(const double *__restrict__ fin, Geom G, int harmonic,
                                                  double *__restrict__ ubar, double *__restrict__ lm)
 {
-    Site o;
-    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
-    pull_sources(G, o);
-    double ub[kFields];
-#pragma unroll
-    for (int F = 0; F < kFields; ++F) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) s += plane(fin, G, F, q)[o.src[q]];
-        ub[F] = s;
-    }
-    double c[7], R[7];
-    lapse_metric(ub, harmonic != 0, c, R);
-#pragma unroll
-    for (int F = 0; F < kFields; ++F) ubar[(size_t)F * G.ps + o.s] = ub[F];
-#pragma unroll
-    for (int F = 0; F < 7; ++F) lm[(size_t)F * G.ps + o.s] = c[F];
-}
-
-// relax one field's 19 distributions and store them at x
-template <int Fld>
-__device__ __forceinline__ void collide_field(const double *__restrict__ fin, double *__restrict__ fout,
-                                              const Geom &G, const Site &o, const Params &P,
-                                              double omega, double srcfac)
-{
-    const double u = P.u[Fld];
-    const double hR = srcfac * P.R[Fld];
-    constexpr bool isK = (Fld >= 7 && Fld <= 12);
-    constexpr int pk = isK ? Fld - 7 : 0;
-    double fl[kQ];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) fl[q] = plane(fin, G, Fld, q)[o.src[q]];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-        double feq;
-        if constexpr (isK) {
-            double cF;
-            switch (q) {
-#define LBNR_CASE(Q_) case Q_: cF = cdot<Q_>(P.F[pk], P.F[6 + pk], P.F[12 + pk]); break;
-                LBNR_CASE(0) LBNR_CASE(1) LBNR_CASE(2) LBNR_CASE(3) LBNR_CASE(4) LBNR_CASE(5)
-                LBNR_CASE(6) LBNR_CASE(7) LBNR_CASE(8) LBNR_CASE(9) LBNR_CASE(10) LBNR_CASE(11)
-                LBNR_CASE(12) LBNR_CASE(13) LBNR_CASE(14) LBNR_CASE(15) LBNR_CASE(16) LBNR_CASE(17)
-                LBNR_CASE(18)
-#undef LBNR_CASE
-            default: cF = 0.0;
-            }
-            feq = wq(q) * (u + 3.0 * cF);
-        } else {
-            feq = wq(q) * u;
-        }
-        const double f = fl[q];
-        plane(fout, G, Fld, q)[o.s] = f - omega * (f - feq) + wq(q) * hR;
-    }
-}
-
-template <int Fld>
-__device__ __forceinline__ void collide_all(const double *__restrict__ fin, double *__restrict__ fout,
-                                            const Geom &G, const Site &o, const Params &P,
-                                            double omega, double srcfac)
-{
-    collide_field<Fld>(fin, fout, G, o, P, omega, srcfac);
-    if constexpr (Fld + 1 < kFields) collide_all<Fld + 1>(fin, fout, G, o, P, omega, srcfac);
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < G.nsite) moments_site64(fin, G, s, harmonic, ubar, lm);
 }
 
 // ---------------------------------------------------------------------------
@@ -100,15 +41,8 @@ __global__ void __launch_bounds__(256) k_collide(const double *__restrict__ fin,
                                                  Geom G, int harmonic, double omega, double srcfac,
                                                  const double *__restrict__ ubar, const double *__restrict__ lm)
 {
-    Site o;
-    if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
-    double ub[kFields];
-#pragma unroll
-    for (int F = 0; F < kFields; ++F) ub[F] = ubar[(size_t)F * G.ps + o.s];
-    Params P;
-    site_params(G, o, harmonic, ub, lm, P);
-    pull_sources(G, o);
-    collide_all<0>(fin, fout, G, o, P, omega, srcfac);
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < G.nsite) collide_site64(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm);
 }
 
 // ---------------------------------------------------------------------------

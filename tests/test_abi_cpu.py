@@ -8,7 +8,8 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lb.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lb.h", "lb_serve.h")]
+PROBE_HEADER = os.path.join(ROOT, "include", "hbm_probe.h")
 
 
 @pytest.fixture(scope="module")
@@ -20,10 +21,12 @@ def lib():
     return lb.load_library()
 
 
-def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", text)))
+def _declared(headers=None, prefix="lb_"):
+    names = set()
+    for h in headers or HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(%s[a-z_0-9]+)\s*\(" % prefix, text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -38,9 +41,39 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_binding_names_match_header(lib):
-    from paper_1505_02037_amd import lb
+    from paper_1505_02037_amd import lb, serve
 
-    assert set(lb.EXPORTS) == set(_declared())
+    assert set(lb.EXPORTS) | set(serve.EXPORTS) == set(_declared())
+
+
+def test_probe_library_exports_its_header():
+    import ctypes as C
+
+    from paper_1505_02037_amd import build
+
+    if not os.path.exists(build.PROBE_LIB):
+        build.build()
+    probe = C.CDLL(build.PROBE_LIB)
+    names = _declared([PROBE_HEADER], prefix="hbm_")
+    assert names == ["hbm_copy_probe"]
+    assert all(hasattr(probe, n) for n in names)
+    ms = C.c_double()
+    assert probe.hbm_copy_probe(C.c_size_t(100), 1, C.byref(ms)) == -1  # not a multiple of 64
+
+
+def test_server_rejects_bad_configs(lib):
+    import ctypes as C
+
+    from paper_1505_02037_amd import serve
+
+    serve._lib()
+    for budget, prec, slots, k in [(0, 0, 4, 8), (1 << 30, 5, 4, 8), (1 << 30, 0, 0, 8), (1 << 30, 0, 4, 0)]:
+        cfg = serve.ServerConfig(budget, prec, slots, k, -1, None)
+        h = C.c_void_p()
+        assert lib.lb_server_create(C.byref(cfg), C.byref(h)) == -1
+        assert not h.value
+    assert lib.lb_server_advance(None, None) == -1
+    lib.lb_server_destroy(None)
 
 
 def test_bad_configs_are_rejected_without_a_device(lib):
