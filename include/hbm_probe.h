@@ -23,6 +23,10 @@ extern "C" {
  * allocation fails, -3 on any other HIP error.  Frees what it allocated. */
 int hbm_copy_probe(size_t bytes, int reps, double *ms);
 
+/* Same, for a read-only stream over one buffer of `bytes` (the result of the
+ * reduction is kept on the device); *ms is the average per pass. */
+int hbm_read_probe(size_t bytes, int reps, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

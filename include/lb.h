@@ -56,6 +56,11 @@ extern "C" {
                           derivative stencil, the geometry, the sources, the
                           flux and the error norms stay FP64 */
 
+#define LB_PATH_AUTO 0   /* the faster of the two on MI355X: split */
+#define LB_PATH_SPLIT 1  /* two launches per step: moments, then collide */
+#define LB_PATH_FUSED 2  /* one z-marching launch per step that also forms
+                            the next step's moments (same results) */
+
 typedef struct lb_handle lb_handle; /* opaque, owned by the library */
 
 typedef struct lb_config {
@@ -67,6 +72,8 @@ typedef struct lb_config {
     int device;      /* HIP device ordinal, or -1 for the current device */
     void *stream;    /* hipStream_t to run on, or NULL: the library creates
                         and owns a stream of default priority */
+    int path;        /* LB_PATH_AUTO, LB_PATH_SPLIT or LB_PATH_FUSED: how a
+                        step is launched; every path gives identical results */
 } lb_config;
 
 /* Allocates two distribution buffers and per-site scratch on the device.

@@ -7,7 +7,8 @@
  *
  *   stage 1  moments      ubar_F = sum_q f_{F,q}            (section "Lattice
  *                                                           Boltzmann Model",
- *                                                           macroscopic moments)
+ *                                                           macroscopic moments),
+ *            summed plane by plane (in-plane, from below, from above)
  *   stage 2  lapse/metric corrected first: R_alpha = -alpha^2 Q (Eq. alfan,
  *            zero shift), R_gamma = -2 alpha K (three-metric equation, zero
  *            shift), alpha = abar + R_alpha/2, gamma = gbar + R_gamma/2
@@ -343,6 +344,10 @@ static void bm_lambda(const double gi[3][3], const double g[3][3], const double 
 #define DIST(arr, F, q, n) ((arr) + ((size_t)(F) * NQ + (size_t)(q)) * (n))
 
 /* stage 1: ubar_F = sum_q f_{F,q} */
+/* The sum over the 19 directions is taken plane by plane: the directions
+ * lying in the site's z-plane (c_z = 0), those arriving from the plane below
+ * (c_z = +1), those arriving from the plane above (c_z = -1), each in index
+ * order, then (in-plane + below) + above. */
 static void stage_moments(lbref *h)
 {
     const size_t n = h->nsite;
@@ -350,9 +355,17 @@ static void stage_moments(lbref *h)
     for (long long ss = 0; ss < (long long)n; ++ss) {
         const size_t x = (size_t)ss;
         for (int F = 0; F < NF; ++F) {
-            double s = 0.0;
-            for (int q = 0; q < NQ; ++q) s += DIST(h->f, F, q, n)[x];
-            FLD(h->ubar, F, n)[x] = s;
+            double in_plane = 0.0, below = 0.0, above = 0.0;
+            for (int q = 0; q < NQ; ++q) {
+                const double f = DIST(h->f, F, q, n)[x];
+                if (CQ[q][2] == 0)
+                    in_plane += f;
+                else if (CQ[q][2] > 0)
+                    below += f;
+                else
+                    above += f;
+            }
+            FLD(h->ubar, F, n)[x] = in_plane + below + above;
         }
     }
 }

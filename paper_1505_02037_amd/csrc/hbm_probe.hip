@@ -20,7 +20,53 @@ __global__ void __launch_bounds__(256) k_copy(const double2 *__restrict__ src, d
     for (; i < n; i += stride) dst[i] = src[i];
 }
 
+__global__ void __launch_bounds__(256) k_read(const double2 *__restrict__ src, size_t n, double *__restrict__ sink)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double2 v = src[i];
+        acc += v.x + v.y;
+    }
+    if (acc != 0.0) sink[blockIdx.x] = acc; // the buffer is zero: never taken, but keeps the loads
+}
+
 } // namespace
+
+extern "C" int hbm_read_probe(size_t bytes, int reps, double *ms)
+{
+    if (!ms || reps < 1 || bytes == 0 || bytes % 64) return -1;
+    void *a = nullptr;
+    double *sink = nullptr;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
+    const dim3 grid((unsigned)cus * 8), block(256);
+    if (hipMalloc(&a, bytes) != hipSuccess) return -2;
+    if (hipMalloc((void **)&sink, grid.x * sizeof(double)) != hipSuccess) {
+        (void)hipFree(a);
+        return -2;
+    }
+    int rc = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float t = 0.f;
+    const size_t n = bytes / sizeof(double2);
+    if (hipMemset(a, 0, bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        rc = -3;
+    } else {
+        hipLaunchKernelGGL(k_read, grid, block, 0, 0, (const double2 *)a, n, sink);
+        (void)hipEventRecord(e0, 0);
+        for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(k_read, grid, block, 0, 0, (const double2 *)a, n, sink);
+        (void)hipEventRecord(e1, 0);
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = -3;
+        *ms = (double)t / reps;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(sink);
+    return rc;
+}
 
 extern "C" int hbm_copy_probe(size_t bytes, int reps, double *ms)
 {

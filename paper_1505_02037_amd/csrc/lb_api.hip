@@ -56,7 +56,10 @@ struct lb_handle {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     void *fbuf[2] = {nullptr, nullptr};   // distribution buffers [16][19][ps] (double or float)
-    double *ubar = nullptr;               // [16][ps]
+    double *ubar = nullptr;               // [16][ps] moments of the current state
+    double *ubar2 = nullptr;              // [16][ps] next step's moments (fused path)
+    bool ubar_valid = false;              // ubar holds the current state's moments
+    bool fused = false;                   // one launch per step
     double *lm = nullptr;                 // [7][ps]
     int cur = 0;                          // buffer holding the current state
     bool initialised = false;
@@ -65,7 +68,8 @@ struct lb_handle {
     // timing
     bool timing = false;
     std::vector<hipEvent_t> events;
-    double ms_moments = 0.0, ms_collide = 0.0;
+    double ms_moments = 0.0, ms_collide = 0.0; // fused path: ms_moments holds the one kernel
+    bool timed_fused = false;
     long long timed_launches = 0;
 };
 
@@ -81,6 +85,7 @@ int validate(const lb_config *c)
     if (!(c->tau > 0.5) || !isfinite(c->tau)) return LB_EINVAL;
     if (c->slicing != LB_SLICING_HARMONIC && c->slicing != LB_SLICING_GEODESIC) return LB_EINVAL;
     if (c->precision != LB_FP64 && c->precision != LB_FP32_DEV) return LB_EINVAL;
+    if (c->path != LB_PATH_AUTO && c->path != LB_PATH_SPLIT && c->path != LB_PATH_FUSED) return LB_EINVAL;
     return LB_OK;
 }
 
@@ -128,6 +133,7 @@ void free_all(lb_handle *h)
     for (int i = 0; i < 2; ++i)
         if (h->fbuf[i]) (void)hipFree(h->fbuf[i]);
     if (h->ubar) (void)hipFree(h->ubar);
+    if (h->ubar2) (void)hipFree(h->ubar2);
     if (h->lm) (void)hipFree(h->lm);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -151,7 +157,7 @@ size_t lb_device_bytes(const lb_config *cfg)
 {
     if (validate(cfg) != LB_OK) return 0;
     const Geom G = geom_of(cfg);
-    return 2 * dist_bytes(G, cfg->precision) + (size_t)(16 + 7) * G.ps * sizeof(double);
+    return 2 * dist_bytes(G, cfg->precision) + (size_t)(16 + 16 + 7) * G.ps * sizeof(double);
 }
 
 int lb_create(const lb_config *cfg, lb_handle **out)
@@ -176,6 +182,11 @@ int lb_create(const lb_config *cfg, lb_handle **out)
     hipError_t e = hipSuccess;
     for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc(&h->fbuf[i], dist_bytes(G, cfg->precision));
     if (e == hipSuccess) e = hipMalloc((void **)&h->ubar, (size_t)16 * G.ps * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->ubar2, (size_t)16 * G.ps * sizeof(double));
+    // the fused launch re-fetches the lines its 16-wide tile rows share with
+    // neighbouring tiles, so the split launches are faster on large lattices:
+    // AUTO selects them
+    h->fused = cfg->path == LB_PATH_FUSED;
     if (e == hipSuccess) e = hipMalloc((void **)&h->lm, (size_t)7 * G.ps * sizeof(double));
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -228,6 +239,7 @@ int lb_init_fields(lb_handle *h, const double *u0, int on_device)
     // the caller may release u0 as soon as this returns
     LB_HIP(hipStreamSynchronize(h->stream));
     h->initialised = true;
+    h->ubar_valid = false;
     h->steps = 0;
     return LB_OK;
 }
@@ -238,16 +250,37 @@ int lb_step(lb_handle *h, long long nsteps)
     if (!h->initialised) return LB_ESTATE;
     if (nsteps == 0) return LB_OK;
     DeviceGuard dg(h->device);
+    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    if (h->fused && !h->ubar_valid) {
+        // the fused step starts from the current state's moments
+        LB_HIP(run_moments(h));
+        h->ubar_valid = true;
+    }
+    const int per_step = h->fused ? 1 : 2;
     if (h->timing) {
-        int rc = ensure_events(h, (size_t)2 * nsteps + 1);
+        int rc = ensure_events(h, (size_t)per_step * nsteps + 1);
         if (rc != LB_OK) return rc;
         LB_HIP(hipEventRecord(h->events[0], h->stream));
     }
     for (long long s = 0; s < nsteps; ++s) {
-        LB_HIP(run_moments(h));
-        if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 1], h->stream));
-        LB_HIP(run_collide(h));
-        if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 2], h->stream));
+        if (h->fused) {
+            if (fp32(h))
+                LB_HIP(lbnr::launch_fused32((const float *)h->fbuf[h->cur], (float *)h->fbuf[h->cur ^ 1], h->G,
+                                            harmonic, h->omega, h->srcfac, h->ubar, h->ubar2, h->stream));
+            else
+                LB_HIP(lbnr::launch_fused64((const double *)h->fbuf[h->cur], (double *)h->fbuf[h->cur ^ 1], h->G,
+                                            harmonic, h->omega, h->srcfac, h->ubar, h->ubar2, h->stream));
+            double *t = h->ubar;
+            h->ubar = h->ubar2;
+            h->ubar2 = t;
+            if (h->timing) LB_HIP(hipEventRecord(h->events[s + 1], h->stream));
+        } else {
+            LB_HIP(run_moments(h));
+            if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 1], h->stream));
+            LB_HIP(run_collide(h));
+            if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 2], h->stream));
+            h->ubar_valid = false;
+        }
         h->cur ^= 1;
         h->steps++;
     }
@@ -256,14 +289,19 @@ int lb_step(lb_handle *h, long long nsteps)
         double tm = 0.0, tc = 0.0;
         for (long long s = 0; s < nsteps; ++s) {
             float a = 0.f, b = 0.f;
-            LB_HIP(hipEventElapsedTime(&a, h->events[2 * s], h->events[2 * s + 1]));
-            LB_HIP(hipEventElapsedTime(&b, h->events[2 * s + 1], h->events[2 * s + 2]));
+            if (h->fused) {
+                LB_HIP(hipEventElapsedTime(&a, h->events[s], h->events[s + 1]));
+            } else {
+                LB_HIP(hipEventElapsedTime(&a, h->events[2 * s], h->events[2 * s + 1]));
+                LB_HIP(hipEventElapsedTime(&b, h->events[2 * s + 1], h->events[2 * s + 2]));
+            }
             tm += a;
             tc += b;
         }
         h->ms_moments = tm / (double)nsteps;
         h->ms_collide = tc / (double)nsteps;
         h->timed_launches = nsteps;
+        h->timed_fused = h->fused;
     }
     return LB_OK;
 }
@@ -359,10 +397,13 @@ int lb_kernel_times(lb_handle *h, const char **names, double *ms, int cap, int *
     if (h->timed_launches == 0) return LB_ESTATE;
     static const char *kNames64[2] = {"lbnr::k_moments", "lbnr::k_collide"};
     static const char *kNames32[2] = {"lbnr::k_moments32", "lbnr::k_collide32"};
-    const char *const *kNames = fp32(h) ? kNames32 : kNames64;
+    static const char *kFused64[1] = {"lbnr::k_fused<double>"};
+    static const char *kFused32[1] = {"lbnr::k_fused<float>"};
+    const char *const *kNames = h->timed_fused ? (fp32(h) ? kFused32 : kFused64) : (fp32(h) ? kNames32 : kNames64);
+    const int nk = h->timed_fused ? 1 : 2;
     const double vals[2] = {h->ms_moments, h->ms_collide};
     int n = 0;
-    for (int i = 0; i < 2 && i < cap; ++i, ++n) {
+    for (int i = 0; i < nk && i < cap; ++i, ++n) {
         if (names) names[i] = kNames[i];
         if (ms) ms[i] = vals[i];
     }

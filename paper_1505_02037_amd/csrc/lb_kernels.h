@@ -32,4 +32,12 @@ hipError_t launch_collide32(const float *fin, float *fout, const Geom &G, int ha
 hipError_t launch_init32(const Geom &G, int harmonic, const double *u0, double *lm, float *fout, hipStream_t st);
 hipError_t launch_gather32(const float *fin, const Geom &G, int field, double *f, hipStream_t st);
 
+// one-launch z-marching step (lb_fused.hip): reads this step's moments
+// ubar_in, writes the post-collision distributions and the next step's
+// moments ubar_out
+hipError_t launch_fused64(const double *fin, double *fout, const Geom &G, int harmonic, double omega, double srcfac,
+                          const double *ubar_in, double *ubar_out, hipStream_t st);
+hipError_t launch_fused32(const float *fin, float *fout, const Geom &G, int harmonic, double omega, double srcfac,
+                          const double *ubar_in, double *ubar_out, hipStream_t st);
+
 } // namespace lbnr

@@ -74,20 +74,18 @@ struct Params {
     double F[18];
 };
 
-__device__ __forceinline__ void site_params(const Geom &G, const Site &o, int harmonic,
-                                            const double ub[kFields], const double *__restrict__ lm,
-                                            Params &P)
+// Collision parameters from the raw moments ub, the corrected lapse/metric c
+// with its right-hand sides Rag (lapse_metric(ub)), and the stencil A, D.
+__device__ __forceinline__ void params_from(const double ub[kFields], const double c[7], const double Rag[7],
+                                            const double A[3], const double D[18], Params &P)
 {
-    double c[7], Rag[7];
-    lapse_metric(ub, harmonic != 0, c, Rag);
 #pragma unroll
     for (int F = 0; F < 7; ++F) {
         P.u[F] = c[F];
         P.R[F] = Rag[F];
     }
     const double alpha = c[0];
-    double A[3], D[18], gi[6], S[6], Om[3], V[3];
-    stencil(G, o, lm, alpha, A, D);
+    double gi[6], S[6], Om[3], V[3];
     sym_inverse(c + 1, gi);
     bm_sources(alpha, c + 1, gi, ub + 7, ub + 13, A, D, S, Om);
 #pragma unroll
@@ -103,6 +101,16 @@ __device__ __forceinline__ void site_params(const Geom &G, const Site &o, int ha
         P.u[13 + k] = V[k];
     }
     bm_flux(alpha, c + 1, gi, V, A, D, P.F);
+}
+
+__device__ __forceinline__ void site_params(const Geom &G, const Site &o, int harmonic,
+                                            const double ub[kFields], const double *__restrict__ lm,
+                                            Params &P)
+{
+    double c[7], Rag[7], A[3], D[18];
+    lapse_metric(ub, harmonic != 0, c, Rag);
+    stencil(G, o, lm, c[0], A, D);
+    params_from(ub, c, Rag, A, D, P);
 }
 
 } // namespace lbnr

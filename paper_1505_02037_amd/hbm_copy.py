@@ -21,17 +21,24 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gib", type=float, default=4.0)
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--copy-only", action="store_true", help="only the copy (counter calibration runs)")
     args = ap.parse_args()
     lib = ctypes.CDLL(LIB)
-    lib.hbm_copy_probe.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    for f in (lib.hbm_copy_probe, lib.hbm_read_probe):
+        f.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     nbytes = int(args.gib * (1 << 30)) // 64 * 64
-    ms = ctypes.c_double()
+    ms, msr = ctypes.c_double(), ctypes.c_double()
     rc = lib.hbm_copy_probe(nbytes, args.reps, ctypes.byref(ms))
+    if rc == 0 and not args.copy_only:
+        rc = lib.hbm_read_probe(nbytes, args.reps, ctypes.byref(msr))
     if rc != 0:
         print(json.dumps({"error": rc}))
         return 1
-    print(json.dumps({"copy_bytes_each_way": nbytes, "ms_per_copy": ms.value,
-                      "GBps_read_plus_write": 2 * nbytes / (ms.value * 1e-3) / 1e9}), flush=True)
+    out = {"copy_bytes_each_way": nbytes, "ms_per_copy": ms.value,
+           "GBps_read_plus_write": 2 * nbytes / (ms.value * 1e-3) / 1e9}
+    if not args.copy_only:
+        out.update({"ms_per_read": msr.value, "GBps_read_only": nbytes / (msr.value * 1e-3) / 1e9})
+    print(json.dumps(out), flush=True)
     return 0
 
 

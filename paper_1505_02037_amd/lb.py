@@ -28,6 +28,9 @@ HARMONIC = 0
 GEODESIC = 1
 FP64 = 0
 FP32_DEV = 1
+PATH_AUTO = 0
+PATH_SPLIT = 1
+PATH_FUSED = 2
 NF = 16
 NQ = 19
 
@@ -49,6 +52,7 @@ class LBConfig(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("device", ctypes.c_int),
         ("stream", ctypes.c_void_p),
+        ("path", ctypes.c_int),
     ]
 
 
@@ -122,9 +126,10 @@ def _ptr(a, nelem: int):
     return ctypes.c_void_p(a.data_ptr()), 0
 
 
-def make_config(nx, ny, nz, tau, slicing=HARMONIC, precision=FP64, device=-1, stream=None) -> LBConfig:
+def make_config(nx, ny, nz, tau, slicing=HARMONIC, precision=FP64, device=-1, stream=None,
+                path=PATH_AUTO) -> LBConfig:
     return LBConfig(LB_D3Q19, int(nx), int(ny), int(nz), float(tau), int(slicing), int(precision),
-                    int(device), ctypes.c_void_p(stream) if stream else None)
+                    int(device), ctypes.c_void_p(stream) if stream else None, int(path))
 
 
 def device_bytes(nx, ny, nz, tau=0.6, precision=FP64) -> int:
@@ -136,12 +141,12 @@ class Lattice:
     """One periodic lattice evolved on the GPU (lb_create ... lb_destroy)."""
 
     def __init__(self, nx: int, ny: int, nz: int, tau: float, slicing: int = HARMONIC,
-                 precision: int = FP64, device: int = -1, stream=None):
+                 precision: int = FP64, device: int = -1, stream=None, path: int = PATH_AUTO):
         lib = load_library()
         self._lib = lib
         self.shape = (nz, ny, nx)
         self.nsite = nx * ny * nz
-        cfg = make_config(nx, ny, nz, tau, slicing, precision, device, stream)
+        cfg = make_config(nx, ny, nz, tau, slicing, precision, device, stream, path)
         h = ctypes.c_void_p()
         _check(lib.lb_create(ctypes.byref(cfg), ctypes.byref(h)), "lb_create")
         self._h = h

@@ -55,7 +55,7 @@ def test_probe_library_exports_its_header():
         build.build()
     probe = C.CDLL(build.PROBE_LIB)
     names = _declared([PROBE_HEADER], prefix="hbm_")
-    assert names == ["hbm_copy_probe"]
+    assert names == ["hbm_copy_probe", "hbm_read_probe"]
     assert all(hasattr(probe, n) for n in names)
     ms = C.c_double()
     assert probe.hbm_copy_probe(C.c_size_t(100), 1, C.byref(ms)) == -1  # not a multiple of 64
@@ -87,6 +87,7 @@ def test_bad_configs_are_rejected_without_a_device(lib):
         lb.make_config(8, 8, 8, 0.6, slicing=7),
         lb.make_config(8, 8, 8, 0.6, precision=9),
         lb.make_config(2048, 2048, 2048, 0.6),  # more than 2^32 sites
+        lb.make_config(8, 8, 8, 0.6, path=3),
     ]
     for cfg in bad:
         h = ctypes.c_void_p(1234)
@@ -115,4 +116,4 @@ def test_device_bytes_matches_layout(lib):
 
     n = 100 * 30 * 7
     ps = (n + 63) // 64 * 64
-    assert lb.device_bytes(100, 30, 7) == (2 * 16 * 19 + 16 + 7) * ps * 8
+    assert lb.device_bytes(100, 30, 7) == (2 * 16 * 19 + 16 + 16 + 7) * ps * 8

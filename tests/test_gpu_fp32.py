@@ -121,6 +121,21 @@ def test_fp32_diagonal_256_cubed():
             assert max(err[0], err[1:7].max(), err[13:16].max()) <= 1e-7, (total, err)
 
 
+def test_fp32_fused_equals_split_bitwise():
+    """The FP32 form's one-launch and two-launch steps run the same arithmetic."""
+    _torch()
+    from paper_1505_02037_amd import lb
+
+    u0 = workloads.random_state(31, 29, 70, seed=12)
+    out = []
+    for path in (1, 2):
+        with lb.Lattice(31, 29, 70, 0.8, precision=lb.FP32_DEV, device=0, path=path) as g:
+            g.init_fields(u0)
+            g.step(7)
+            out.append((g.moments(), g.distributions()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 def test_fp32_error_norms_and_kernel_names():
     torch = _torch()
     u0 = workloads.random_state(12, 10, 8, seed=4)
@@ -129,7 +144,7 @@ def test_fp32_error_norms_and_kernel_names():
         g.init_fields(u0)
         g.set_timing(True)
         g.step(2)
-        assert set(g.kernel_times()) == {"lbnr::k_moments32", "lbnr::k_collide32"}
+        assert set(g.kernel_times()) == {"lbnr::k_moments32", "lbnr::k_collide32"}  # 12 x 10: split path
         u = g.moments()
         nr = g.error_norms(torch.from_numpy(ref).cuda())
     assert np.array_equal(nr["max_abs"], np.abs(u - ref).reshape(16, -1).max(axis=1))

@@ -31,28 +31,28 @@ def _torch():
     return torch
 
 
-def _gpu_lattice(shape, tau, slicing):
+def _gpu_lattice(shape, tau, slicing, path=0):
     from paper_1505_02037_amd import lb
 
     nz, ny, nx = shape
-    return lb.Lattice(nx, ny, nz, tau, slicing=slicing, device=0)
+    return lb.Lattice(nx, ny, nz, tau, slicing=slicing, device=0, path=path)
 
 
 def _say(msg):
     print(msg, flush=True)
 
 
-def _both(u0, tau, slicing, horizons):
+def _both(u0, tau, slicing, horizons, path=0):
     """Yield (n, gpu moments, gpu distributions, oracle moments, oracle distributions)."""
     shape = u0.shape[1:]
     nz, ny, nx = shape
     o = oracle.Oracle(nx, ny, nz, tau, slicing)
     o.init_fields(u0)
-    with _gpu_lattice(shape, tau, slicing) as g:
+    with _gpu_lattice(shape, tau, slicing, path) as g:
         g.init_fields(u0)
         done = 0
         for n in horizons:
-            _say(f"  step to {n} on {nx}x{ny}x{nz} tau={tau} slicing={slicing}")
+            _say(f"  step to {n} on {nx}x{ny}x{nz} tau={tau} slicing={slicing} path={path}")
             g.step(n - done)
             o.step(n - done)
             done = n
@@ -75,28 +75,34 @@ CASES = [
     ("random_2x3x1", (1, 3, 2), 0.55, oracle.HARMONIC, 4),
     ("random_1x1x1", (1, 1, 1), 0.9, oracle.HARMONIC, 5),
     ("random_1x9x2", (2, 9, 1), 0.8, oracle.GEODESIC, 6),
+    # several 14 x 14 tiles with ragged edges, two z-chunks (64 + 6 planes)
+    ("random_33x29x70", (70, 29, 33), 0.7, oracle.HARMONIC, 7),
+    ("random_geodesic_28x15x3", (3, 15, 28), 0.9, oracle.GEODESIC, 8),
 ]
+PATHS = {"split": 1, "fused": 2}
 
 
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("name,shape,tau,slicing,seed", CASES, ids=[c[0] for c in CASES])
-def test_random_state_bitwise(name, shape, tau, slicing, seed):
+def test_random_state_bitwise(name, shape, tau, slicing, seed, path):
     _torch()
-    _say(f"[parity] {name}")
+    _say(f"[parity] {name} path={path}")
     nz, ny, nx = shape
     u0 = workloads.random_state(nx, ny, nz, seed=seed, amp=0.05)
-    for n, ug, fg, uo, fo in _both(u0, tau, slicing, (0, 1, 2, 10, 30)):
+    for n, ug, fg, uo, fo in _both(u0, tau, slicing, (0, 1, 2, 10, 30), PATHS[path]):
         _assert_equal(fg, fo, f"{name} distributions at step {n}")
         _assert_equal(ug, uo, f"{name} moments at step {n}")
 
 
-def test_gauge_wave_1d_full_horizon():
+@pytest.mark.parametrize("path", list(PATHS))
+def test_gauge_wave_1d_full_horizon(path):
     """1D gauge wave, A = 0.01, d = N = 100, tau = 0.6, ten crossings (1000
     steps): equal to the oracle at every crossing, including after the
     grid-scale instability has grown (non-finite values compared as equal)."""
     _torch()
-    _say("[parity] gauge_wave_1d 100x1x1 tau=0.6 1000 steps")
+    _say(f"[parity] gauge_wave_1d 100x1x1 tau=0.6 1000 steps path={path}")
     u0 = workloads.gauge_wave_x(100, 1, 1, 0.01, 100.0)
-    for n, ug, fg, uo, fo in _both(u0, 0.6, oracle.HARMONIC, range(0, 1001, 100)):
+    for n, ug, fg, uo, fo in _both(u0, 0.6, oracle.HARMONIC, range(0, 1001, 100), PATHS[path]):
         _assert_equal(fg, fo, f"distributions at step {n}")
         _assert_equal(ug, uo, f"moments at step {n}")
 
@@ -126,7 +132,7 @@ def test_diagonal_wave_256_cubed_plane_by_plane():
     o.step(steps)
     uo = o.moments()[:, 0]
     u3 = torch.from_numpy(u2).cuda().expand(16, n, n, n).contiguous()
-    with _gpu_lattice((n, n, n), 0.6, oracle.HARMONIC) as g:
+    with _gpu_lattice((n, n, n), 0.6, oracle.HARMONIC) as g:  # the default path, as benchmarked
         g.init_fields(u3)
         del u3
         g.step(steps)
@@ -190,14 +196,34 @@ def test_device_pointers_and_stream():
     _assert_equal(fo.cpu().numpy(), o.distributions(), "distributions")
 
 
-def test_kernel_timing_reports_both_kernels():
+def test_kernel_timing_names_the_launched_kernels():
     _torch()
     from paper_1505_02037_amd import lb
 
-    with lb.Lattice(32, 32, 32, 0.6, device=0) as g:
-        g.init_fields(workloads.gauge_wave_x(32, 32, 32, 0.1, 32))
-        g.set_timing(True)
-        g.step(3)
-        t = g.kernel_times()
-    assert set(t) == {"lbnr::k_moments", "lbnr::k_collide"}
-    assert all(v > 0 for v in t.values())
+    for path, names in ((1, {"lbnr::k_moments", "lbnr::k_collide"}), (2, {"lbnr::k_fused<double>"})):
+        with lb.Lattice(32, 32, 32, 0.6, device=0, path=path) as g:
+            g.init_fields(workloads.gauge_wave_x(32, 32, 32, 0.1, 32))
+            g.set_timing(True)
+            g.step(3)
+            t = g.kernel_times()
+        assert set(t) == names
+        assert all(v > 0 for v in t.values())
+
+
+def test_fused_and_split_paths_agree_after_moments_calls():
+    """Interleaving output calls (which recompute the moments) with fused steps
+    leaves the evolution unchanged."""
+    _torch()
+    from paper_1505_02037_amd import lb
+
+    u0 = workloads.random_state(30, 16, 9, seed=31)
+    res = []
+    for path, probe in ((1, False), (2, False), (2, True)):
+        with lb.Lattice(30, 16, 9, 0.7, device=0, path=path) as g:
+            g.init_fields(u0)
+            for _ in range(4):
+                g.step(3)
+                if probe:
+                    g.moments()
+            res.append(g.distributions())
+    assert np.array_equal(res[0], res[1]) and np.array_equal(res[1], res[2])
