@@ -157,7 +157,8 @@ size_t lb_device_bytes(const lb_config *cfg)
 {
     if (validate(cfg) != LB_OK) return 0;
     const Geom G = geom_of(cfg);
-    return 2 * dist_bytes(G, cfg->precision) + (size_t)(16 + 16 + 7) * G.ps * sizeof(double);
+    const size_t scratch = cfg->path == LB_PATH_FUSED ? 16 + 16 + 7 : 16 + 7;
+    return 2 * dist_bytes(G, cfg->precision) + scratch * G.ps * sizeof(double);
 }
 
 int lb_create(const lb_config *cfg, lb_handle **out)
@@ -182,11 +183,11 @@ int lb_create(const lb_config *cfg, lb_handle **out)
     hipError_t e = hipSuccess;
     for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc(&h->fbuf[i], dist_bytes(G, cfg->precision));
     if (e == hipSuccess) e = hipMalloc((void **)&h->ubar, (size_t)16 * G.ps * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&h->ubar2, (size_t)16 * G.ps * sizeof(double));
     // the fused launch re-fetches the lines its 16-wide tile rows share with
     // neighbouring tiles, so the split launches are faster on large lattices:
     // AUTO selects them
     h->fused = cfg->path == LB_PATH_FUSED;
+    if (e == hipSuccess && h->fused) e = hipMalloc((void **)&h->ubar2, (size_t)16 * G.ps * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->lm, (size_t)7 * G.ps * sizeof(double));
     if (e != hipSuccess) {
         (void)hipGetLastError();

@@ -116,4 +116,5 @@ def test_device_bytes_matches_layout(lib):
 
     n = 100 * 30 * 7
     ps = (n + 63) // 64 * 64
-    assert lb.device_bytes(100, 30, 7) == (2 * 16 * 19 + 16 + 16 + 7) * ps * 8
+    assert lb.device_bytes(100, 30, 7) == (2 * 16 * 19 + 16 + 7) * ps * 8
+    assert lb.device_bytes(100, 30, 7, precision=lb.FP32_DEV) == (16 * 19 + 16 + 7) * ps * 8
