@@ -118,3 +118,20 @@ def test_device_bytes_matches_layout(lib):
     ps = (n + 63) // 64 * 64
     assert lb.device_bytes(100, 30, 7) == (2 * 16 * 19 + 16 + 7) * ps * 8
     assert lb.device_bytes(100, 30, 7, precision=lb.FP32_DEV) == (16 * 19 + 16 + 7) * ps * 8
+
+
+def test_build_entry_reaches_both_build_steps(monkeypatch):
+    """__graft_entry__.build() calls the HIP build and the oracle build (the
+    compilers are replaced by recorders here; the real build runs outside
+    the test suite)."""
+    import importlib
+
+    import __graft_entry__
+
+    calls = []
+    hip_build = importlib.import_module("paper_1505_02037_amd.build")
+    oracle_build = importlib.import_module("oracle.build")
+    monkeypatch.setattr(hip_build, "build", lambda verbose=False: calls.append("hip"))
+    monkeypatch.setattr(oracle_build, "build", lambda verbose=False: calls.append("oracle"))
+    __graft_entry__.build()
+    assert calls == ["hip", "oracle"]

@@ -107,6 +107,19 @@ def test_gauge_wave_1d_full_horizon(path):
         _assert_equal(ug, uo, f"moments at step {n}")
 
 
+@pytest.mark.parametrize("path", list(PATHS))
+def test_linear_wave_bitwise(path):
+    """Linear wave (geodesic slicing, A = 1e-5, tau = 4.5): exercises the
+    gamma_yy/gamma_zz, K_yy/K_zz, D_xyy/D_xzz and V_x terms the gauge waves
+    leave at zero."""
+    _torch()
+    _say(f"[parity] linear wave 40x16x15 path={path}")
+    u0 = workloads.linear_wave_x(40, 16, 15, 1e-5, 40.0)
+    for n, ug, fg, uo, fo in _both(u0, 4.5, oracle.GEODESIC, (1, 25, 100), PATHS[path]):
+        _assert_equal(fg, fo, f"distributions at step {n}")
+        _assert_equal(ug, uo, f"moments at step {n}")
+
+
 def test_gauge_wave_3d_x_128_resolution_pieces():
     """x-wave on 64 x 8 x 8 (a 3D lattice) equals the oracle at several
     horizons at each tau of the 3D gauge-wave series."""

@@ -219,3 +219,48 @@ def test_first_order_convergence_at_constant_diffusivity():
         errs.append(np.abs(u[1] - ua[1]).max() / np.abs(ua[1] - 1).max())
     slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert all(0.85 < s < 1.2 for s in slopes), slopes
+
+
+def test_linear_wave_growth_phase_and_geodesic_lapse():
+    """Linear (gravitational) wave (section "Linear Wave"), geodesic slicing:
+    the lapse stays 1 to rounding, the b-mode of gamma_yy travels at light
+    speed and grows at the same Chapman-Enskog rate (tau - 1/2) kappa^2 / 6
+    as the gauge wave (K_yy's flux at speed 1 against gamma_yy's diffusion)."""
+    N, tau = 100, 1.5
+    kappa = 2 * math.pi / N
+    o = oracle.Oracle(N, 1, 1, tau, oracle.GEODESIC)
+    o.init_fields(workloads.linear_wave_x(N, 1, 1, 1e-6, N))
+
+    def mode(u):
+        x = np.arange(N)
+        return ((u[4, 0, 0, :] - 1.0) * np.exp(-2j * np.pi * x / N)).sum() * 2 / N
+
+    a0 = mode(o.moments())
+    o.step(N // 4)
+    a1 = mode(o.moments())
+    assert abs(np.angle(a1 / a0) + math.pi / 2) < 0.04
+    o.step(200 - N // 4)
+    u = o.moments()
+    growth = math.log(abs(mode(u)) / abs(a0)) / 200
+    assert abs(growth / ((tau - 0.5) * kappa ** 2 / 6) - 1) < 0.02
+    assert np.abs(u[0] - 1.0).max() <= 1e-15
+    # gamma_yy + gamma_zz - 2 stays second order in the amplitude
+    assert np.abs(u[4] + u[6] - 2.0).max() <= 1e-10
+
+
+@pytest.mark.slow
+def test_linear_wave_paper_setup_lifetime():
+    """Paper setup (800 sites per wavelength, A = 1e-5, tau = 4.5, geodesic):
+    the deviation of gamma_yy from the analytic wave reaches 10 % after a
+    life-time of the same order as the gauge wave's (~2e3 steps)."""
+    N, tau, A = 800, 4.5, 1e-5
+    o = oracle.Oracle(N, 1, 1, tau, oracle.GEODESIC)
+    o.init_fields(workloads.linear_wave_x(N, 1, 1, A, N))
+    first = None
+    for n in range(0, 3001, 100):
+        u = o.moments()
+        ua = workloads.linear_wave_x(N, 1, 1, A, N, t=n)
+        if first is None and np.abs(u[4] - ua[4]).max() / np.abs(ua[4] - 1).max() > 0.10:
+            first = n
+        o.step(100)
+    assert first is not None and 1500 <= first <= 3000, first
