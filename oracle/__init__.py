@@ -5,8 +5,9 @@ CPU-baseline leg of the benchmark import this package.  It is a plain, slow,
 scalar C implementation (``lbref.c``) written from the paper, sharing no code
 with the GPU library; this module only marshals arguments through ctypes.
 
-Arrays: u is float64 (16, nz, ny, nx); f is float64 (16, 19, nz, ny, nx),
-the distributions at the current time (after streaming).
+Arrays: u is float64 (16, nz, ny, nx); f is float64 (16, Q, nz, ny, nx),
+the distributions at the current time (after streaming), Q = 19 on D3Q19 and
+Q = 9 on D2Q9 (which takes nz = 1).
 """
 
 from __future__ import annotations
@@ -20,6 +21,8 @@ from .build import LIB, build
 
 HARMONIC = 0
 GEODESIC = 1
+D3Q19 = 19
+D2Q9 = 9
 NF = 16
 NQ = 19
 
@@ -38,6 +41,11 @@ def _load():
     lib.lbref_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                  ctypes.c_int, ctypes.POINTER(P)]
     lib.lbref_create.restype = ctypes.c_int
+    lib.lbref_create_lattice.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_int, ctypes.POINTER(P)]
+    lib.lbref_create_lattice.restype = ctypes.c_int
+    lib.lbref_lattice.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
+    lib.lbref_lattice.restype = ctypes.c_int
     lib.lbref_destroy.argtypes = [P]
     lib.lbref_destroy.restype = None
     lib.lbref_init_fields.argtypes = [P, dp]
@@ -69,13 +77,15 @@ def _check(rc: int, what: str) -> None:
 class Oracle:
     """One periodic lattice evolved by the CPU oracle."""
 
-    def __init__(self, nx: int, ny: int, nz: int, tau: float, slicing: int = HARMONIC):
+    def __init__(self, nx: int, ny: int, nz: int, tau: float, slicing: int = HARMONIC, lattice: int = D3Q19):
         lib = _load()
         self._lib = lib
         self.shape = (nz, ny, nx)
         self.nsite = nx * ny * nz
+        self.nq = int(lattice)
         h = ctypes.c_void_p()
-        _check(lib.lbref_create(nx, ny, nz, float(tau), int(slicing), ctypes.byref(h)), "create")
+        _check(lib.lbref_create_lattice(int(lattice), nx, ny, nz, float(tau), int(slicing), ctypes.byref(h)),
+               "create")
         self._h = h
 
     def close(self) -> None:
@@ -103,13 +113,13 @@ class Oracle:
         return out
 
     def distributions(self) -> np.ndarray:
-        out = np.empty((NF, NQ) + self.shape, dtype=np.float64)
+        out = np.empty((NF, self.nq) + self.shape, dtype=np.float64)
         _check(self._lib.lbref_get_distributions(self._h, _dp(out)), "get_distributions")
         return out
 
     def set_distributions(self, f: np.ndarray) -> None:
         f = np.ascontiguousarray(f, dtype=np.float64)
-        assert f.shape == (NF, NQ) + self.shape
+        assert f.shape == (NF, self.nq) + self.shape
         _check(self._lib.lbref_set_distributions(self._h, _dp(f)), "set_distributions")
 
     @property
@@ -123,6 +133,15 @@ def lattice_d3q19():
     w = np.empty(19, dtype=np.float64)
     lib.lbref_lattice_d3q19(c, _dp(w))
     return np.array(list(c), dtype=np.int64).reshape(19, 3), w
+
+
+def lattice(q: int):
+    """Velocities (Q, 3) and weights (Q,) of the oracle's D3Q19 or D2Q9 table."""
+    lib = _load()
+    c = (ctypes.c_int * (3 * q))()
+    w = np.empty(q, dtype=np.float64)
+    _check(0 if lib.lbref_lattice(int(q), c, _dp(w)) == q else -1, "lattice")
+    return np.array(list(c), dtype=np.int64).reshape(q, 3), w
 
 
 def point_rhs(alpha, g6, K6, V, A, D18, slicing: int = HARMONIC) -> dict:

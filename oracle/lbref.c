@@ -39,11 +39,11 @@
 #endif
 
 #define NF 16
-#define NQ 19
+#define NQMAX 19
 
 /* D3Q19 velocities in the paper's column order, upper sign first
  * (section "Lattice Boltzmann Model", D3Q19 matrix). */
-static const int CQ[NQ][3] = {
+static const int CQ19[19][3] = {
     {0, 0, 0},
     {1, 0, 0},  {-1, 0, 0},
     {0, 1, 0},  {0, -1, 0},
@@ -57,12 +57,30 @@ static const int CQ[NQ][3] = {
 };
 
 /* weights 1/3, 1/18 (axes), 1/36 (face diagonals); c_s^2 = 1/3 */
-static double weight(int q)
-{
-    if (q == 0) return 1.0 / 3.0;
-    if (q <= 6) return 1.0 / 18.0;
-    return 1.0 / 36.0;
-}
+static const double W19[19] = {
+    1.0 / 3.0,
+    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+};
+
+/* D2Q9 velocities in the paper's column order (section "Lattice Boltzmann
+ * Model", D2Q9 matrix): c0 = 0, c1,2 = (+-1, 0), c3,4 = (0, +-1),
+ * c5,6 = +-(1, -1), c7,8 = +-(1, 1); upper sign first.  c_z = 0. */
+static const int CQ9[9][3] = {
+    {0, 0, 0},
+    {1, 0, 0},  {-1, 0, 0},
+    {0, 1, 0},  {0, -1, 0},
+    {1, -1, 0}, {-1, 1, 0},
+    {1, 1, 0},  {-1, -1, 0},
+};
+
+/* weights 4/9, 1/9 (axes), 1/36 (diagonals); c_s^2 = 1/3 */
+static const double W9[9] = {
+    4.0 / 9.0,
+    1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+};
 
 /* symmetric storage: (xx, xy, xz, yy, yz, zz) */
 static const int PAIR_I[6] = {0, 0, 0, 1, 1, 2};
@@ -74,13 +92,16 @@ static int sym(int i, int j)
 }
 
 struct lbref {
+    int nq;                 /* 19 (D3Q19) or 9 (D2Q9) */
+    const int (*cq)[3];     /* velocities */
+    const double *w;        /* weights */
     int nx, ny, nz;
     size_t nsite;
     double tau, omega, srcfac;
     int slicing;
     long long nstep;
-    double *f;     /* [NF][NQ][nsite] current distributions */
-    double *fpost; /* [NF][NQ][nsite] post-collision scratch */
+    double *f;     /* [NF][nq][nsite] current distributions */
+    double *fpost; /* [NF][nq][nsite] post-collision scratch */
     double *ubar;  /* [NF][nsite] zeroth moments */
     double *ucor;  /* [NF][nsite] moments with half source */
     double *R;     /* [NF][nsite] right-hand sides */
@@ -341,10 +362,10 @@ static void bm_lambda(const double gi[3][3], const double g[3][3], const double 
 /* ------------------------------------------------------------------------ */
 
 #define FLD(arr, F, n) ((arr) + (size_t)(F) * (n))
-#define DIST(arr, F, q, n) ((arr) + ((size_t)(F) * NQ + (size_t)(q)) * (n))
+#define DIST(arr, F, q, n) ((arr) + ((size_t)(F) * (size_t)h->nq + (size_t)(q)) * (n))
 
 /* stage 1: ubar_F = sum_q f_{F,q} */
-/* The sum over the 19 directions is taken plane by plane: the directions
+/* The sum over the directions is taken plane by plane: the directions
  * lying in the site's z-plane (c_z = 0), those arriving from the plane below
  * (c_z = +1), those arriving from the plane above (c_z = -1), each in index
  * order, then (in-plane + below) + above. */
@@ -356,11 +377,11 @@ static void stage_moments(lbref *h)
         const size_t x = (size_t)ss;
         for (int F = 0; F < NF; ++F) {
             double in_plane = 0.0, below = 0.0, above = 0.0;
-            for (int q = 0; q < NQ; ++q) {
+            for (int q = 0; q < h->nq; ++q) {
                 const double f = DIST(h->f, F, q, n)[x];
-                if (CQ[q][2] == 0)
+                if (h->cq[q][2] == 0)
                     in_plane += f;
-                else if (CQ[q][2] > 0)
+                else if (h->cq[q][2] > 0)
                     below += f;
                 else
                     above += f;
@@ -490,10 +511,10 @@ static double feq_at(const lbref *h, int F, int q, size_t c)
     if (F >= 7 && F <= 12) {
         const int p = F - 7;
         double cF = 0.0;
-        for (int m = 0; m < 3; ++m) cF += (double)CQ[q][m] * FLD(h->flux, m * 6 + p, n)[c];
-        return weight(q) * (u + 3.0 * cF); /* 1/c_s^2 = 3 */
+        for (int m = 0; m < 3; ++m) cF += (double)h->cq[q][m] * FLD(h->flux, m * 6 + p, n)[c];
+        return h->w[q] * (u + 3.0 * cF); /* 1/c_s^2 = 3 */
     }
-    return weight(q) * u;
+    return h->w[q] * u;
 }
 
 /* stage 4: BGK collision with source (Eq. numlb), then periodic streaming */
@@ -506,10 +527,10 @@ static void stage_collide_stream(lbref *h)
         const size_t c = (size_t)ss;
         for (int F = 0; F < NF; ++F) {
             const double hR = srcfac * FLD(h->R, F, n)[c];
-            for (int q = 0; q < NQ; ++q) {
+            for (int q = 0; q < h->nq; ++q) {
                 const double f = DIST(h->f, F, q, n)[c];
                 const double feq = feq_at(h, F, q, c);
-                const double src = weight(q) * hR;
+                const double src = h->w[q] * hR;
                 DIST(h->fpost, F, q, n)[c] = f - omega * (f - feq) + src;
             }
         }
@@ -517,12 +538,12 @@ static void stage_collide_stream(lbref *h)
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < h->nz; ++z)
         for (int F = 0; F < NF; ++F)
-            for (int q = 0; q < NQ; ++q)
+            for (int q = 0; q < h->nq; ++q)
                 for (int y = 0; y < h->ny; ++y)
                     for (int x = 0; x < h->nx; ++x) {
-                        const size_t src = site_index(h, wrap(x - CQ[q][0], h->nx),
-                                                      wrap(y - CQ[q][1], h->ny),
-                                                      wrap(z - CQ[q][2], h->nz));
+                        const size_t src = site_index(h, wrap(x - h->cq[q][0], h->nx),
+                                                      wrap(y - h->cq[q][1], h->ny),
+                                                      wrap(z - h->cq[q][2], h->nz));
                         DIST(h->f, F, q, n)[site_index(h, x, y, z)] = DIST(h->fpost, F, q, n)[src];
                     }
 }
@@ -533,13 +554,23 @@ static void stage_collide_stream(lbref *h)
 
 int lbref_create(int nx, int ny, int nz, double tau, int slicing, lbref **out)
 {
+    return lbref_create_lattice(LBREF_D3Q19, nx, ny, nz, tau, slicing, out);
+}
+
+int lbref_create_lattice(int lattice, int nx, int ny, int nz, double tau, int slicing, lbref **out)
+{
     if (!out) return LBREF_EINVAL;
     *out = NULL;
+    if (lattice != LBREF_D3Q19 && lattice != LBREF_D2Q9) return LBREF_EINVAL;
     if (nx < 1 || ny < 1 || nz < 1) return LBREF_EINVAL;
+    if (lattice == LBREF_D2Q9 && nz != 1) return LBREF_EINVAL;
     if (!(tau > 0.5)) return LBREF_EINVAL;
     if (slicing != LBREF_SLICING_HARMONIC && slicing != LBREF_SLICING_GEODESIC) return LBREF_EINVAL;
     lbref *h = (lbref *)calloc(1, sizeof(lbref));
     if (!h) return LBREF_ENOMEM;
+    h->nq = lattice;
+    h->cq = lattice == LBREF_D2Q9 ? CQ9 : CQ19;
+    h->w = lattice == LBREF_D2Q9 ? W9 : W19;
     h->nx = nx;
     h->ny = ny;
     h->nz = nz;
@@ -549,8 +580,8 @@ int lbref_create(int nx, int ny, int nz, double tau, int slicing, lbref **out)
     h->srcfac = 1.0 - 0.5 * h->omega; /* (1 - dt/(2 tau)) */
     h->slicing = slicing;
     const size_t n = h->nsite;
-    h->f = (double *)calloc(n * NF * NQ, sizeof(double));
-    h->fpost = (double *)calloc(n * NF * NQ, sizeof(double));
+    h->f = (double *)calloc(n * NF * (size_t)h->nq, sizeof(double));
+    h->fpost = (double *)calloc(n * NF * (size_t)h->nq, sizeof(double));
     h->ubar = (double *)calloc(n * NF, sizeof(double));
     h->ucor = (double *)calloc(n * NF, sizeof(double));
     h->R = (double *)calloc(n * NF, sizeof(double));
@@ -609,8 +640,8 @@ int lbref_init_fields(lbref *h, const double *u0)
         const size_t c = (size_t)ss;
         for (int F = 0; F < NF; ++F) {
             const double hR = 0.5 * FLD(h->R, F, n)[c];
-            for (int q = 0; q < NQ; ++q)
-                DIST(h->f, F, q, n)[c] = feq_at(h, F, q, c) - weight(q) * hR;
+            for (int q = 0; q < h->nq; ++q)
+                DIST(h->f, F, q, n)[c] = feq_at(h, F, q, c) - h->w[q] * hR;
         }
     }
     h->nstep = 0;
@@ -643,26 +674,34 @@ int lbref_moments(lbref *h, double *u_out)
 int lbref_get_distributions(const lbref *h, double *f_out)
 {
     if (!h || !f_out) return LBREF_EINVAL;
-    memcpy(f_out, h->f, h->nsite * NF * NQ * sizeof(double));
+    memcpy(f_out, h->f, h->nsite * NF * (size_t)h->nq * sizeof(double));
     return LBREF_OK;
 }
 
 int lbref_set_distributions(lbref *h, const double *f_in)
 {
     if (!h || !f_in) return LBREF_EINVAL;
-    memcpy(h->f, f_in, h->nsite * NF * NQ * sizeof(double));
+    memcpy(h->f, f_in, h->nsite * NF * (size_t)h->nq * sizeof(double));
     return LBREF_OK;
 }
 
 long long lbref_nsteps_done(const lbref *h) { return h ? h->nstep : -1; }
 
-void lbref_lattice_d3q19(int *c, double *w)
+void lbref_lattice_d3q19(int *c, double *w) { (void)lbref_lattice(LBREF_D3Q19, c, w); }
+
+int lbref_lattice(int lattice, int *c, double *w)
 {
-    for (int q = 0; q < NQ; ++q) {
-        for (int m = 0; m < 3; ++m) c[q * 3 + m] = CQ[q][m];
-        w[q] = weight(q);
+    if (lattice != LBREF_D3Q19 && lattice != LBREF_D2Q9) return LBREF_EINVAL;
+    const int (*cq)[3] = lattice == LBREF_D2Q9 ? CQ9 : CQ19;
+    const double *wq = lattice == LBREF_D2Q9 ? W9 : W19;
+    for (int q = 0; q < lattice; ++q) {
+        for (int m = 0; m < 3; ++m) c[q * 3 + m] = cq[q][m];
+        w[q] = wq[q];
     }
+    return lattice;
 }
+
+int lbref_lattice_q(const lbref *h) { return h ? h->nq : LBREF_EINVAL; }
 
 int lbref_point_rhs(const double *in, int slicing, double *out)
 {
@@ -697,13 +736,13 @@ int lbref_point_rhs(const double *in, int slicing, double *out)
 
 void lbref_point_feq(int kind, double u, const double *F, double *feq19)
 {
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < 19; ++q) {
         if (kind == 1) {
             double cF = 0.0;
-            for (int m = 0; m < 3; ++m) cF += (double)CQ[q][m] * F[m];
-            feq19[q] = weight(q) * (u + 3.0 * cF);
+            for (int m = 0; m < 3; ++m) cF += (double)CQ19[q][m] * F[m];
+            feq19[q] = W19[q] * (u + 3.0 * cF);
         } else {
-            feq19[q] = weight(q) * u;
+            feq19[q] = W19[q] * u;
         }
     }
 }

@@ -13,7 +13,8 @@
  *                 symmetric pairs in the order xx, xy, xz, yy, yz, zz.
  *   u arrays:     u[field][z][y][x], x fastest, float64.
  *   f arrays:     f[field][q][z][y][x], the distributions at the current time
- *                 (after streaming), D3Q19 directions q in the paper's order.
+ *                 (after streaming), directions q in the paper's order of the
+ *                 lattice (D3Q19, or D2Q9 on an nx x ny x 1 lattice).
  *   boundaries:   periodic in all three directions (section "Gauge choices").
  *
  * Return codes: 0 on success, negative on error (see LBREF_E*).
@@ -29,13 +30,20 @@ extern "C" {
 #define LBREF_EINVAL (-1)
 #define LBREF_ENOMEM (-2)
 
+#define LBREF_D3Q19 19 /* section "Lattice Boltzmann Model", D3Q19 matrix */
+#define LBREF_D2Q9 9   /* section "Lattice Boltzmann Model", D2Q9 matrix; nz = 1 */
+
 #define LBREF_SLICING_HARMONIC 0 /* Q = tr K   (section "Gauge choices") */
 #define LBREF_SLICING_GEODESIC 1 /* Q = 0 */
 
 typedef struct lbref lbref;
 
-/* nx, ny, nz >= 1; tau > 1/2 (relaxation time in units of dt). */
+/* nx, ny, nz >= 1; tau > 1/2 (relaxation time in units of dt).  D3Q19. */
 int lbref_create(int nx, int ny, int nz, double tau, int slicing, lbref **out);
+/* The same on a chosen lattice: LBREF_D3Q19, or LBREF_D2Q9 (requires nz = 1). */
+int lbref_create_lattice(int lattice, int nx, int ny, int nz, double tau, int slicing, lbref **out);
+/* number of directions of the handle's lattice */
+int lbref_lattice_q(const lbref *h);
 void lbref_destroy(lbref *h);
 
 /* Initial distributions from macroscopic fields u0 (16 x nsite):
@@ -48,7 +56,7 @@ int lbref_step(lbref *h, long long nsteps);
 /* Macroscopic fields u = sum_q f_q + R/2 at the current time (16 x nsite). */
 int lbref_moments(lbref *h, double *u_out);
 
-/* Copy the current distributions out / in (16 x 19 x nsite). */
+/* Copy the current distributions out / in (16 x Q x nsite). */
 int lbref_get_distributions(const lbref *h, double *f_out);
 int lbref_set_distributions(lbref *h, const double *f_in);
 
@@ -58,6 +66,8 @@ long long lbref_nsteps_done(const lbref *h);
 
 /* D3Q19 velocities c[q*3+m] and weights w[q]. */
 void lbref_lattice_d3q19(int *c, double *w);
+/* velocities and weights of a lattice (c: 3 Q ints, w: Q doubles); returns Q */
+int lbref_lattice(int lattice, int *c, double *w);
 
 /* Right-hand sides and flux of the Bona-Masso system at one point.
  * in  (37): alpha, gamma[6], K[6], V[3], A[3], D[18] with D[k*6+pair] = D_k(ij)
@@ -65,7 +75,7 @@ void lbref_lattice_d3q19(int *c, double *w);
  *           lambda[18] with lambda[k*6+pair] = lambda^k_(ij) */
 int lbref_point_rhs(const double *in, int slicing, double *out);
 
-/* Equilibrium of one field at one point: kind 0 -> w_q u (alpha, gamma, V);
+/* Equilibrium of one field at one point on D3Q19: kind 0 -> w_q u (alpha, gamma, V);
  * kind 1 -> w_q (u + c_q.F / c_s^2) (K components), F = flux vector (3). */
 void lbref_point_feq(int kind, double u, const double *F, double *feq19);
 

@@ -1,7 +1,9 @@
 """Pins of the oracle's lattice tables and equilibria.
 
-- The D3Q19 table equals the paper's printed matrix and weights (golden file).
-- Lattice isotropy to fourth order (exact rational identities of D3Q19).
+- The D3Q19 and D2Q9 tables equal the paper's printed matrices and weights
+  (golden files).
+- Lattice isotropy to fourth order (exact rational identities of D3Q19 in
+  three dimensions and of D2Q9 in two).
 - Equilibria (Eqs. alfa..ekst, zero shift) reproduce the field value as zeroth
   moment and the flux as first moment, with second moment c_s^2 u delta.
 """
@@ -15,6 +17,7 @@ import pytest
 import oracle
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "d3q19_paper.txt")
+GOLDEN9 = os.path.join(os.path.dirname(__file__), "golden", "d2q9_paper.txt")
 
 
 def _golden():
@@ -26,6 +29,55 @@ def _golden():
         q, cx, cy, cz, w = line.split()
         rows.append((int(q), (int(cx), int(cy), int(cz)), Fraction(w)))
     return rows
+
+
+def _golden9():
+    rows = []
+    for line in open(GOLDEN9):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        q, cx, cy, w = line.split()
+        rows.append((int(q), (int(cx), int(cy), 0), Fraction(w)))
+    return rows
+
+
+def test_d2q9_matches_paper_table():
+    c, w = oracle.lattice(9)
+    rows = _golden9()
+    assert len(rows) == 9
+    for q, cv, wf in rows:
+        assert tuple(c[q]) == cv, q
+        assert w[q] == float(wf), q
+    c19, w19 = oracle.lattice(19)
+    c19b, w19b = oracle.lattice_d3q19()
+    assert np.array_equal(c19, c19b) and np.array_equal(w19, w19b)
+
+
+def test_d2q9_isotropy_exact():
+    rows = _golden9()
+    cs2 = Fraction(1, 3)
+    d = lambda a, b: 1 if a == b else 0  # noqa: E731
+    assert sum(w for _, _, w in rows) == 1
+    for a in range(2):
+        assert sum(w * c[a] for _, c, w in rows) == 0
+        for b in range(2):
+            assert sum(w * c[a] * c[b] for _, c, w in rows) == cs2 * d(a, b)
+            for g in range(2):
+                assert sum(w * c[a] * c[b] * c[g] for _, c, w in rows) == 0
+                for e in range(2):
+                    m4 = sum(w * c[a] * c[b] * c[g] * c[e] for _, c, w in rows)
+                    assert m4 == cs2 * cs2 * (d(a, b) * d(g, e) + d(a, g) * d(b, e) + d(a, e) * d(b, g))
+
+
+def test_d3q19_projects_onto_d2q9():
+    """Summing the D3Q19 weights over the directions that share (c_x, c_y)
+    gives the D2Q9 weights: on a lattice one site thick in z the two lattices
+    carry the same dynamics (the basis of the D2Q9 / D3Q19 scheme pin)."""
+    proj = {}
+    for _, c, w in _golden():
+        proj[(c[0], c[1])] = proj.get((c[0], c[1]), 0) + w
+    assert proj == {(c[0], c[1]): w for _, c, w in _golden9()}
 
 
 def test_d3q19_matches_paper_table():

@@ -16,6 +16,12 @@
 - The paper's gauge-wave life-time (about 2e3 steps until the error exceeds
   10 %) at its own setup, and first-order convergence at constant numerical
   diffusivity (section "Relaxation Time and Numerical Diffusivity").
+- The linear wave: Chapman-Enskog growth, light-speed phase, unit lapse under
+  geodesic slicing, and its life-time at the paper's setup.
+- D2Q9: on a lattice one site thick in z the D3Q19 step summed over the
+  directions sharing (c_x, c_y) is the D2Q9 step, so the two oracles agree to
+  rounding; flat space and the collision budget on D2Q9; the paper's D2Q9
+  gauge wave.
 """
 
 import json
@@ -264,3 +270,92 @@ def test_linear_wave_paper_setup_lifetime():
             first = n
         o.step(100)
     assert first is not None and 1500 <= first <= 3000, first
+
+
+def _d3q19_grouped(f19):
+    """Sum D3Q19 distributions over the directions that share (c_x, c_y), in
+    the D2Q9 order."""
+    c19, _ = oracle.lattice(19)
+    c9, _ = oracle.lattice(9)
+    out = np.zeros((f19.shape[0], 9) + f19.shape[2:])
+    for q9 in range(9):
+        for q in range(19):
+            if tuple(c19[q][:2]) == tuple(c9[q9][:2]):
+                out[:, q9] += f19[:, q]
+    return out
+
+
+@pytest.mark.parametrize("slicing", [oracle.HARMONIC, oracle.GEODESIC])
+def test_d2q9_equals_d3q19_one_site_thick(slicing):
+    """On an nx x ny x 1 lattice the D3Q19 directions with c_z = +-1 stream
+    within the plane, and summing the D3Q19 step over the directions that
+    share (c_x, c_y) gives the D2Q9 step (weights 4/9, 1/9, 1/36 and zero
+    c_z-moments in every group).  The two oracles therefore agree to rounding,
+    distributions grouped and moments, on a random two-dimensional state."""
+    u0 = workloads.random_state(13, 11, 1, seed=21, amp=0.05)
+    o19 = oracle.Oracle(13, 11, 1, 1.0, slicing)
+    o9 = oracle.Oracle(13, 11, 1, 1.0, slicing, lattice=oracle.D2Q9)
+    for o in (o19, o9):
+        o.init_fields(u0)
+    for n in (0, 1, 6):
+        if n:
+            o19.step(n - (1 if n == 6 else 0))
+            o9.step(n - (1 if n == 6 else 0))
+        f9 = o9.distributions()
+        assert f9.shape == (16, 9, 1, 11, 13)
+        assert np.abs(_d3q19_grouped(o19.distributions()) - f9).max() <= 1e-14
+        assert np.abs(o19.moments() - o9.moments()).max() <= 1e-14
+
+
+def test_d2q9_minkowski_and_budget():
+    """Flat space is a fixed point of the D2Q9 step, and the D2Q9 collision
+    adds exactly R to every field's distribution sum."""
+    u0 = workloads.minkowski(6, 5, 1)
+    o = oracle.Oracle(6, 5, 1, 0.8, lattice=oracle.D2Q9)
+    o.init_fields(u0)
+    o.step(200)
+    assert np.abs(o.moments() - u0).max() <= 2.3e-16
+    u0 = workloads.random_state(7, 6, 1, seed=4, amp=0.05)
+    o = oracle.Oracle(7, 6, 1, 0.7, lattice=oracle.D2Q9)
+    o.init_fields(u0)
+    o.step(2)
+    u = o.moments()
+    ubar = o.distributions().sum(axis=1)
+    o.step(1)
+    after = o.distributions().sum(axis=(1, 2, 3, 4))
+    assert np.allclose(after, (2.0 * u - ubar).sum(axis=(1, 2, 3)), rtol=0, atol=1e-12)
+
+
+def test_d2q9_rejects_thick_lattice():
+    with pytest.raises(RuntimeError):
+        oracle.Oracle(4, 4, 2, 0.8, lattice=oracle.D2Q9)
+    with pytest.raises(RuntimeError):
+        oracle.Oracle(4, 4, 1, 0.8, lattice=7)
+
+
+@pytest.mark.slow
+def test_d2q9_paper_gauge_wave():
+    """The paper ran its gauge wave on D2Q9 (section "Gauge Wave"): at its
+    setup the D2Q9 run follows the D3Q19 run to rounding and reaches 10 %
+    error after about 2e3 steps."""
+    N, A, tau = 800, 1e-3, 4.5
+    u0 = workloads.gauge_wave_x(N, 1, 1, A, N)
+    o9 = oracle.Oracle(N, 1, 1, tau, lattice=oracle.D2Q9)
+    o19 = oracle.Oracle(N, 1, 1, tau)
+    for o in (o9, o19):
+        o.init_fields(u0)
+    life = None
+    for n in range(100, 3001, 100):
+        o9.step(100)
+        o19.step(100)
+        u9 = o9.moments()
+        ua = workloads.gauge_wave_x(N, 1, 1, A, N, t=n)
+        if life is None and np.abs(u9[1] - ua[1]).max() / np.abs(ua[1] - 1).max() > 0.10:
+            life = n
+        # K and V are fed by differences of the O(1) lapse and metric, so
+        # their rounding differences are absolute at the metric's ulp scale;
+        # the scheme's fastest mode at tau = 4.5 (growth ~3.1e-3 per step)
+        # amplifies them by up to ~1e4 over 3000 steps
+        d = np.abs(u9 - o19.moments()).max(axis=(1, 2, 3))
+        assert d.max() <= 2e-15 * math.exp(3.2e-3 * n)
+    assert life is not None and 1500 <= life <= 3000, life
