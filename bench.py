@@ -35,7 +35,7 @@ FIELDS, Q = 16, 19
 ALG_BYTES_PER_SITE = {"fp64": 2 * FIELDS * Q * 8, "fp32": 2 * FIELDS * Q * 4}
 
 
-STEP_SOURCES = ("lb_api.hip", "lb_device.h", "lb_fp32.hip", "lb_fp64.hip", "lb_kernels.h", "lb_site.h")
+STEP_SOURCES = ("lb_api.hip", "lb_device.h", "lb_fp32.hip", "lb_fp64.hip", "lb_kernels.h", "lb_site.h", "lb_step.h")
 
 
 def kernel_source_hash() -> str:

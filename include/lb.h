@@ -5,8 +5,9 @@
  *
  * The library evolves the 16 fields u = (alpha, gamma_ij, K_ij, V_k) of the
  * Bona-Masso system (section "Bona-Masso evolution equations", vacuum, zero
- * shift) with one distribution per field on the D3Q19 velocity set (section
- * "Lattice Boltzmann Model"), BGK collision with a source term (Eq. numlb),
+ * shift) with one distribution per field on the D3Q19 velocity set, or on
+ * D2Q9 for lattices one site thick in z (section "Lattice Boltzmann Model"),
+ * BGK collision with a source term (Eq. numlb),
  * the per-field equilibria and sources (Eqs. alfa .. ekstsor) and the
  * half-source macroscopic moments, on a periodic lattice (section "Gauge
  * choices").  Lattice units: dt = dx = 1.
@@ -15,8 +16,9 @@
  *   fields   0 alpha | 1..6 gamma (xx,xy,xz,yy,yz,zz) | 7..12 K (same order)
  *            | 13..15 V (x,y,z)
  *   u arrays double, [16][nz][ny][nx], x fastest, no padding.
- *   f arrays double, [16][19][nz][ny][nx], the distributions at the current
- *            time after streaming, D3Q19 directions in the paper's order.
+ *   f arrays double, [16][Q][nz][ny][nx], the distributions at the current
+ *            time after streaming, the lattice's Q directions in the paper's
+ *            order.
  *   pointers "on_device" = 1: a device pointer on the handle's device (the
  *            call is stream-ordered on the handle's stream, which does not
  *            wait for other streams: device inputs must be complete when the
@@ -43,7 +45,10 @@ extern "C" {
 #define LB_EDEVICE (-3)   /* a HIP call failed (message in lb_last_error) */
 #define LB_ESTATE (-4)    /* handle not initialised with lb_init_fields */
 
-#define LB_D3Q19 19
+#define LB_D3Q19 19 /* section "Lattice Boltzmann Model", D3Q19 matrix */
+#define LB_D2Q9 9    /* section "Lattice Boltzmann Model", D2Q9 matrix: the
+                        paper's gauge-wave lattice; requires nz = 1 and the
+                        split path (LB_PATH_AUTO or LB_PATH_SPLIT) */
 
 #define LB_SLICING_HARMONIC 0 /* Q = tr K  (harmonic slicing)  */
 #define LB_SLICING_GEODESIC 1 /* Q = 0     (geodesic slicing)  */
@@ -64,7 +69,7 @@ extern "C" {
 typedef struct lb_handle lb_handle; /* opaque, owned by the library */
 
 typedef struct lb_config {
-    int lattice;     /* LB_D3Q19 */
+    int lattice;     /* LB_D3Q19 or LB_D2Q9 */
     int nx, ny, nz;  /* periodic extents, each >= 1 */
     double tau;      /* relaxation time in units of dt (Eq. lbe); > 1/2 */
     int slicing;     /* LB_SLICING_HARMONIC or LB_SLICING_GEODESIC */
@@ -100,7 +105,8 @@ int lb_step(lb_handle *h, long long nsteps);
  * ([16][nz][ny][nx]).  Synchronises the handle's stream. */
 int lb_moments(lb_handle *h, double *u_out, int on_device);
 
-/* The distributions at the current time into f_out ([16][19][nz][ny][nx]).
+/* The distributions at the current time into f_out ([16][Q][nz][ny][nx],
+ * Q = 19 on D3Q19, 9 on D2Q9, directions in the paper's order).
  * Synchronises the handle's stream. */
 int lb_get_distributions(lb_handle *h, double *f_out, int on_device);
 

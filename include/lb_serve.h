@@ -75,9 +75,10 @@ int lb_server_create(const lb_server_config *cfg, lb_server **out);
 size_t lb_server_request_bytes(const lb_server *s, const lb_config *cfg);
 
 /* Queues an evolution of nsteps >= 0 steps from u0 (host, copied).  cfg's
- * lattice, extents, tau and slicing are used; its precision, device and stream
- * are ignored (the server's apply).  LB_EINVAL if cfg is invalid or the
- * request can never fit the arena.  *id receives the request id. */
+ * lattice (LB_D3Q19 only), extents, tau and slicing are used; its precision,
+ * device and stream are ignored (the server's apply).  LB_EINVAL if cfg is
+ * invalid, names another lattice, or the request can never fit the arena.
+ * *id receives the request id. */
 int lb_server_submit(lb_server *s, const lb_config *cfg, const double *u0, long long nsteps,
                      unsigned long long *id);
 

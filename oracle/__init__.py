@@ -23,6 +23,8 @@ HARMONIC = 0
 GEODESIC = 1
 D3Q19 = 19
 D2Q9 = 9
+MATTER_TENSOR = 0
+MATTER_FLUID = 1
 NF = 16
 NQ = 19
 
@@ -58,6 +60,8 @@ def _load():
     lib.lbref_lattice_d3q19.argtypes = [ctypes.POINTER(ctypes.c_int), dp]
     lib.lbref_lattice_d3q19.restype = None
     lib.lbref_point_rhs.argtypes = [dp, ctypes.c_int, dp]
+    lib.lbref_point_rhs_matter.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, dp]
+    lib.lbref_set_matter.argtypes = [P, ctypes.c_int, dp, ctypes.c_int]
     lib.lbref_point_feq.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
     lib.lbref_point_feq.restype = None
     lib.lbref_num_threads.argtypes = []
@@ -122,6 +126,21 @@ class Oracle:
         assert f.shape == (NF, self.nq) + self.shape
         _check(self._lib.lbref_set_distributions(self._h, _dp(f)), "set_distributions")
 
+    def set_matter(self, M, kind: int = MATTER_TENSOR) -> None:
+        """Matter in lattice units: kind MATTER_TENSOR, M = G^00, G^0_k, G_ij
+        (10 values); kind MATTER_FLUID, M = (rho, P).  M of shape (ncomp,)
+        applies at every site, (ncomp, nz, ny, nx) per site; None: vacuum."""
+        if M is None:
+            _check(self._lib.lbref_set_matter(self._h, int(kind), None, 0), "set_matter")
+            return
+        nc = 2 if kind == MATTER_FLUID else 10
+        M = np.ascontiguousarray(M, dtype=np.float64)
+        if M.shape == (nc,):
+            _check(self._lib.lbref_set_matter(self._h, int(kind), _dp(M), 0), "set_matter")
+        else:
+            assert M.shape == (nc,) + self.shape, M.shape
+            _check(self._lib.lbref_set_matter(self._h, int(kind), _dp(M), 1), "set_matter")
+
     @property
     def steps_done(self) -> int:
         return int(self._lib.lbref_nsteps_done(self._h))
@@ -144,13 +163,20 @@ def lattice(q: int):
     return np.array(list(c), dtype=np.int64).reshape(q, 3), w
 
 
-def point_rhs(alpha, g6, K6, V, A, D18, slicing: int = HARMONIC) -> dict:
-    """Right-hand sides and flux of the Bona-Masso system at one point."""
+def point_rhs(alpha, g6, K6, V, A, D18, slicing: int = HARMONIC, matter=None, kind: int = MATTER_TENSOR) -> dict:
+    """Right-hand sides and flux of the Bona-Masso system at one point;
+    matter: None (vacuum), G^00, G^0_k, G_ij (10 values, kind MATTER_TENSOR)
+    or (rho, P) (kind MATTER_FLUID)."""
     lib = _load()
     inp = np.concatenate([[alpha], g6, K6, V, A, D18]).astype(np.float64)
     assert inp.shape == (37,)
     out = np.empty(34, dtype=np.float64)
-    _check(lib.lbref_point_rhs(_dp(inp), int(slicing), _dp(out)), "point_rhs")
+    if matter is None:
+        _check(lib.lbref_point_rhs(_dp(inp), int(slicing), _dp(out)), "point_rhs")
+    else:
+        G = np.ascontiguousarray(matter, dtype=np.float64)
+        assert G.shape == ((2,) if kind == MATTER_FLUID else (10,))
+        _check(lib.lbref_point_rhs_matter(_dp(inp), int(kind), _dp(G), int(slicing), _dp(out)), "point_rhs")
     return {
         "R_alpha": out[0],
         "R_gamma": out[1:7].copy(),

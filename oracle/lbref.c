@@ -106,7 +106,22 @@ struct lbref {
     double *ucor;  /* [NF][nsite] moments with half source */
     double *R;     /* [NF][nsite] right-hand sides */
     double *flux;  /* [3][6][nsite] alpha lambda^k_(ij) */
+    int matter;      /* 0: vacuum; 1: the same values at every site; 2: values per site */
+    int matter_kind; /* LBREF_MATTER_TENSOR (10 values) or LBREF_MATTER_FLUID (rho, P) */
+    double matter_uniform[10];
+    double *matter_field; /* [ncomp][nsite] when matter == 2 */
 };
+
+static int matter_ncomp(int kind) { return kind == LBREF_MATTER_FLUID ? 2 : 10; }
+
+/* the matter values at site c (NULL in vacuum) */
+static const double *matter_at(const lbref *h, size_t c, double M[10])
+{
+    if (h->matter == 0) return NULL;
+    if (h->matter == 1) return h->matter_uniform;
+    for (int m = 0; m < matter_ncomp(h->matter_kind); ++m) M[m] = h->matter_field[(size_t)m * h->nsite + c];
+    return M;
+}
 
 static size_t site_index(const lbref *h, int x, int y, int z)
 {
@@ -165,8 +180,47 @@ static double trace_up(const double gi[3][3], const double K[3][3])
 /* ------------------------------------------------------------------------ */
 
 /*
+ * Matter part of the sources (section "Bona-Masso evolution equations", the
+ * energy-momentum terms of S_ij and Omega_k; units c = 8 pi G = 1).
+ *   kind 0 (tensor): M holds G^00, G^0_k (k = x, y, z), G_ij (xx, xy, xz,
+ *          yy, yz, zz);
+ *   kind 1 (perfect fluid at rest in the slicing, section "Expansion of flat
+ *          universe"): M holds rho and P, and G^00 = rho / alpha^2,
+ *          G^0_k = 0, G_ij = P gamma_ij at the site's lapse and metric.
+ * With R4_ij = G_ij - gamma_ij/2 (-alpha^2 G^00 + tr G), tr G = gamma^{ij} G_ij,
+ * S_ij gains -R4_ij and gamma_ij/4 (2 alpha^2 G^00) from its bracket, and
+ * Omega_k gains alpha (alpha G^0_k).  The matter part is added after the
+ * vacuum part, as one sum per component:
+ *   S_ij += gamma_ij/4 (2 alpha^2 G^00) - R4_ij,  Omega_k += alpha (alpha G^0_k)
+ * (for the fluid alpha^2 G^00 is rho itself and Omega_k is unchanged).
+ */
+static void matter_sources(double alpha, const double gi[3][3], const double g[3][3], int kind,
+                           const double *M, double S6[6], double Om[3])
+{
+    double Gm[3][3];
+    double a2G;
+    if (kind == 1) {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Gm[i][j] = M[1] * g[i][j];
+        a2G = M[0];
+    } else {
+        full3(M + 4, Gm);
+        a2G = alpha * alpha * M[0];
+    }
+    const double trG = trace_up(gi, Gm);
+    for (int p = 0; p < 6; ++p) {
+        const int i = PAIR_I[p], j = PAIR_J[p];
+        const double R4 = Gm[i][j] - 0.5 * g[i][j] * (-a2G + trG);
+        S6[p] += 0.25 * g[i][j] * (2.0 * a2G) - R4;
+    }
+    if (kind == 0)
+        for (int k = 0; k < 3; ++k) Om[k] += alpha * (alpha * M[1 + k]);
+}
+
+/*
  * S_ij and Omega_k from the extrinsic-curvature and momentum-variable
- * equations with G = 0 and B = 0.  Index conventions: the first index of D is
+ * equations with B = 0 (zero shift); the matter part (G) is added by
+ * matter_sources when a matter field is set.  Index conventions: the first index of D is
  * the derivative index; indices are raised with the inverse 3-metric.
  *   K_i^j = g^{jl} K_il          D^k_ij = g^{kl} D_lij     D_ki^j = g^{jl} D_kil
  *   D_k^{ij} = g^{il} D_kl^j     D_kr^r, D^j_jk, D_k^{kr} their traces
@@ -176,7 +230,7 @@ static double trace_up(const double gi[3][3], const double K[3][3])
  */
 static void bm_sources(double alpha, const double gi[3][3], const double g[3][3],
                        const double K[3][3], const double V[3], const double A[3],
-                       const double D[3][3][3], double S6[6], double Om[3])
+                       const double D[3][3][3], int mkind, const double *M, double S6[6], double Om[3])
 {
     double Kmix[3][3], Dup[3][3][3], Dmix[3][3][3], Dkup[3][3][3], Gam[3][3][3];
     double d1[3], d2[3], d3[3], gc[3], Au[3], Vu[3];
@@ -315,6 +369,7 @@ static void bm_sources(double alpha, const double gi[3][3], const double g[3][3]
         for (int r = 0; r < 3; ++r) o3 += Kmix[k][r] * (d1[r] - 2.0 * d2[r]);
         Om[k] = alpha * (o1 + o2 - o3);
     }
+    if (M) matter_sources(alpha, gi, g, mkind, M, S6, Om);
 }
 
 /*
@@ -464,7 +519,8 @@ static void site_curvature(const lbref *h, const double *lm, const double *kv,
     full3(g6, g);
     full3(Kb6, Kb);
     inv3(g6, gi);
-    bm_sources(alpha, gi, g, Kb, Vb, A, D, S6, Om);
+    double M[10];
+    bm_sources(alpha, gi, g, Kb, Vb, A, D, h->matter_kind, matter_at(h, c, M), S6, Om);
     for (int p = 0; p < 6; ++p) {
         RK[p] = alpha * S6[p];
         Kc[p] = halfstep ? Kb6[p] + 0.5 * RK[p] : Kb6[p];
@@ -603,6 +659,7 @@ void lbref_destroy(lbref *h)
     free(h->ucor);
     free(h->R);
     free(h->flux);
+    free(h->matter_field);
     free(h);
 }
 
@@ -687,6 +744,30 @@ int lbref_set_distributions(lbref *h, const double *f_in)
 
 long long lbref_nsteps_done(const lbref *h) { return h ? h->nstep : -1; }
 
+int lbref_set_matter(lbref *h, int kind, const double *M, int per_site)
+{
+    if (!h) return LBREF_EINVAL;
+    if (kind != LBREF_MATTER_TENSOR && kind != LBREF_MATTER_FLUID) return LBREF_EINVAL;
+    if (!M) {
+        h->matter = 0;
+        return LBREF_OK;
+    }
+    const int nc = matter_ncomp(kind);
+    if (per_site) {
+        if (!h->matter_field) {
+            h->matter_field = (double *)malloc(h->nsite * 10 * sizeof(double));
+            if (!h->matter_field) return LBREF_ENOMEM;
+        }
+        memcpy(h->matter_field, M, h->nsite * (size_t)nc * sizeof(double));
+        h->matter = 2;
+    } else {
+        memcpy(h->matter_uniform, M, (size_t)nc * sizeof(double));
+        h->matter = 1;
+    }
+    h->matter_kind = kind;
+    return LBREF_OK;
+}
+
 void lbref_lattice_d3q19(int *c, double *w) { (void)lbref_lattice(LBREF_D3Q19, c, w); }
 
 int lbref_lattice(int lattice, int *c, double *w)
@@ -705,6 +786,12 @@ int lbref_lattice_q(const lbref *h) { return h ? h->nq : LBREF_EINVAL; }
 
 int lbref_point_rhs(const double *in, int slicing, double *out)
 {
+    return lbref_point_rhs_matter(in, LBREF_MATTER_TENSOR, NULL, slicing, out);
+}
+
+int lbref_point_rhs_matter(const double *in, int kind, const double *M, int slicing, double *out)
+{
+    if (kind != LBREF_MATTER_TENSOR && kind != LBREF_MATTER_FLUID) return LBREF_EINVAL;
     if (!in || !out) return LBREF_EINVAL;
     const double alpha = in[0];
     double g6[6], K6[6], V[3], A[3], D[3][3][3], g[3][3], gi[3][3], K[3][3];
@@ -725,7 +812,7 @@ int lbref_point_rhs(const double *in, int slicing, double *out)
     const double Q = (slicing == LBREF_SLICING_HARMONIC) ? trace_up(gi, K) : 0.0;
     out[0] = -(alpha * alpha * Q);
     for (int p = 0; p < 6; ++p) out[1 + p] = -2.0 * alpha * K6[p];
-    bm_sources(alpha, gi, g, K, V, A, D, S6, Om);
+    bm_sources(alpha, gi, g, K, V, A, D, kind, M, S6, Om);
     for (int p = 0; p < 6; ++p) out[7 + p] = alpha * S6[p];
     for (int k = 0; k < 3; ++k) out[13 + k] = Om[k];
     bm_lambda(gi, g, V, A, D, lam);

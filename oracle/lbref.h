@@ -62,6 +62,22 @@ int lbref_set_distributions(lbref *h, const double *f_in);
 
 long long lbref_nsteps_done(const lbref *h);
 
+/* Matter (energy-momentum tensor G, units c = 8 pi G = 1; section
+ * "Bona-Masso evolution equations"), in lattice units, of one of two kinds:
+ *   LBREF_MATTER_TENSOR: 10 values, G^00, G^0_k (x, y, z), G_ij (xx, xy, xz,
+ *                        yy, yz, zz);
+ *   LBREF_MATTER_FLUID:  2 values, rho and P of a perfect fluid at rest in
+ *                        the slicing: G^00 = rho / alpha^2, G^0_k = 0,
+ *                        G_ij = P gamma_ij at the site's lapse and metric
+ *                        (section "Expansion of flat universe").
+ * per_site = 0: M holds the values used at every site; 1: M is
+ * [ncomp][nsite].  M = NULL returns to vacuum.  The matter set enters every
+ * later evaluation of the sources (initialisation, steps, moments) until it
+ * is changed. */
+#define LBREF_MATTER_TENSOR 0
+#define LBREF_MATTER_FLUID 1
+int lbref_set_matter(lbref *h, int kind, const double *M, int per_site);
+
 /* ---- point routines, exposed so tests can pin the formulas ---- */
 
 /* D3Q19 velocities c[q*3+m] and weights w[q]. */
@@ -74,6 +90,9 @@ int lbref_lattice(int lattice, int *c, double *w);
  * out (34): R_alpha, R_gamma[6], R_K[6] (= alpha S_ij), Omega[3],
  *           lambda[18] with lambda[k*6+pair] = lambda^k_(ij) */
 int lbref_point_rhs(const double *in, int slicing, double *out);
+/* The same with matter M of the given kind (as for lbref_set_matter; NULL:
+ * vacuum). */
+int lbref_point_rhs_matter(const double *in, int kind, const double *M, int slicing, double *out);
 
 /* Equilibrium of one field at one point on D3Q19: kind 0 -> w_q u (alpha, gamma, V);
  * kind 1 -> w_q (u + c_q.F / c_s^2) (K components), F = flux vector (3). */

@@ -78,8 +78,10 @@ namespace {
 int validate(const lb_config *c)
 {
     if (!c) return LB_EINVAL;
-    if (c->lattice != LB_D3Q19) return LB_EINVAL;
+    if (c->lattice != LB_D3Q19 && c->lattice != LB_D2Q9) return LB_EINVAL;
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return LB_EINVAL;
+    // D2Q9 is a lattice one site thick in z, stepped by the split launches
+    if (c->lattice == LB_D2Q9 && (c->nz != 1 || c->path == LB_PATH_FUSED)) return LB_EINVAL;
     const double n = (double)c->nx * (double)c->ny * (double)c->nz;
     if (n > 4294967295.0) return LB_EINVAL; // 32-bit site indices
     if (!(c->tau > 0.5) || !isfinite(c->tau)) return LB_EINVAL;
@@ -97,14 +99,15 @@ Geom geom_of(const lb_config *c)
     G.nz = c->nz;
     G.nsite = (uint32_t)((size_t)c->nx * c->ny * c->nz);
     G.ps = round_up(G.nsite, 64);
+    G.nq = c->lattice;
     return G;
 }
 
 size_t elem_bytes(int precision) { return precision == LB_FP32_DEV ? sizeof(float) : sizeof(double); }
-size_t dist_bytes(const Geom &G, int precision) { return (size_t)16 * 19 * G.ps * elem_bytes(precision); }
+size_t dist_bytes(const Geom &G, int precision) { return (size_t)16 * G.nq * G.ps * elem_bytes(precision); }
 
 // the buffer not holding the current state: free scratch between steps
-// (at least 16 x 19 x 4 bytes per site)
+// (at least 16 x 9 x 4 bytes per site: 18 doubles)
 double *spare(lb_handle *h) { return (double *)h->fbuf[h->cur ^ 1]; }
 
 bool fp32(const lb_handle *h) { return h->cfg.precision == LB_FP32_DEV; }
@@ -330,8 +333,8 @@ int lb_get_distributions(lb_handle *h, double *f_out, int on_device)
     DeviceGuard dg(h->device);
     const Geom &G = h->G;
     if (fp32(h)) {
-        // one field at a time: the spare buffer holds 19 doubles per site
-        const size_t n = (size_t)19 * G.nsite;
+        // one field at a time: the spare buffer holds Q doubles per site
+        const size_t n = (size_t)G.nq * G.nsite;
         for (int F = 0; F < 16; ++F) {
             double *dst = on_device ? f_out + (size_t)F * n : spare(h);
             LB_HIP(lbnr::launch_gather32((const float *)h->fbuf[h->cur], G, F, dst, h->stream));
@@ -346,7 +349,7 @@ int lb_get_distributions(lb_handle *h, double *f_out, int on_device)
     double *dst = on_device ? f_out : spare(h);
     LB_HIP(lbnr::launch_gather((const double *)h->fbuf[h->cur], G, dst, h->stream));
     if (!on_device)
-        LB_HIP(hipMemcpyAsync(f_out, dst, (size_t)16 * 19 * G.nsite * sizeof(double), hipMemcpyDeviceToHost,
+        LB_HIP(hipMemcpyAsync(f_out, dst, (size_t)16 * G.nq * G.nsite * sizeof(double), hipMemcpyDeviceToHost,
                               h->stream));
     LB_HIP(hipStreamSynchronize(h->stream));
     return LB_OK;
@@ -396,11 +399,15 @@ int lb_kernel_times(lb_handle *h, const char **names, double *ms, int cap, int *
 {
     if (!h || !count) return LB_EINVAL;
     if (h->timed_launches == 0) return LB_ESTATE;
-    static const char *kNames64[2] = {"lbnr::k_moments", "lbnr::k_collide"};
-    static const char *kNames32[2] = {"lbnr::k_moments32", "lbnr::k_collide32"};
+    static const char *kNames64[2] = {"lbnr::k_moments<lbnr::D3Q19>", "lbnr::k_collide<lbnr::D3Q19>"};
+    static const char *kNames32[2] = {"lbnr::k_moments32<lbnr::D3Q19>", "lbnr::k_collide32<lbnr::D3Q19>"};
+    static const char *kNames64q9[2] = {"lbnr::k_moments<lbnr::D2Q9>", "lbnr::k_collide<lbnr::D2Q9>"};
+    static const char *kNames32q9[2] = {"lbnr::k_moments32<lbnr::D2Q9>", "lbnr::k_collide32<lbnr::D2Q9>"};
     static const char *kFused64[1] = {"lbnr::k_fused<double>"};
     static const char *kFused32[1] = {"lbnr::k_fused<float>"};
-    const char *const *kNames = h->timed_fused ? (fp32(h) ? kFused32 : kFused64) : (fp32(h) ? kNames32 : kNames64);
+    const bool q9 = h->G.nq == LB_D2Q9;
+    const char *const *kNames = h->timed_fused ? (fp32(h) ? kFused32 : kFused64)
+                                               : (fp32(h) ? (q9 ? kNames32q9 : kNames32) : (q9 ? kNames64q9 : kNames64));
     const int nk = h->timed_fused ? 1 : 2;
     const double vals[2] = {h->ms_moments, h->ms_collide};
     int n = 0;

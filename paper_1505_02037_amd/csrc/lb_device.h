@@ -15,30 +15,61 @@
 namespace lbnr {
 
 constexpr int kFields = 16;
-constexpr int kQ = 19;
 
-// D3Q19 velocities in the paper's column order, upper sign first
-// (section "Lattice Boltzmann Model").
-__host__ __device__ constexpr int cx(int q)
-{
-    constexpr int v[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-    return v[q];
-}
-__host__ __device__ constexpr int cy(int q)
-{
-    constexpr int v[kQ] = {0, 0, 0, 1, -1, 0, 0, -1, 1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
-    return v[q];
-}
-__host__ __device__ constexpr int cz(int q)
-{
-    constexpr int v[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, -1, 1, 1, -1, -1, 1, 1, -1};
-    return v[q];
-}
-// weights 1/3 (rest), 1/18 (axes), 1/36 (face diagonals); c_s^2 = 1/3
-__host__ __device__ constexpr double wq(int q)
-{
-    return q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
-}
+// Lattices (section "Lattice Boltzmann Model"): velocities in the paper's
+// column order, upper sign first in every pair; c_s^2 = 1/3 on both.
+struct D3Q19 {
+    static constexpr int Q = 19;
+    __host__ __device__ static constexpr int cx(int q)
+    {
+        constexpr int v[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+        return v[q];
+    }
+    __host__ __device__ static constexpr int cy(int q)
+    {
+        constexpr int v[Q] = {0, 0, 0, 1, -1, 0, 0, -1, 1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+        return v[q];
+    }
+    __host__ __device__ static constexpr int cz(int q)
+    {
+        constexpr int v[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, -1, 1, 1, -1, -1, 1, 1, -1};
+        return v[q];
+    }
+    // 1/3 (rest), 1/18 (axes), 1/36 (face diagonals)
+    __host__ __device__ static constexpr double w(int q)
+    {
+        return q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+};
+
+// D2Q9 on a lattice one site thick in z (c_z = 0)
+struct D2Q9 {
+    static constexpr int Q = 9;
+    __host__ __device__ static constexpr int cx(int q)
+    {
+        constexpr int v[Q] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+        return v[q];
+    }
+    __host__ __device__ static constexpr int cy(int q)
+    {
+        constexpr int v[Q] = {0, 0, 0, 1, -1, -1, 1, 1, -1};
+        return v[q];
+    }
+    __host__ __device__ static constexpr int cz(int) { return 0; }
+    // 4/9 (rest), 1/9 (axes), 1/36 (diagonals)
+    __host__ __device__ static constexpr double w(int q)
+    {
+        return q == 0 ? 4.0 / 9.0 : (q <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+};
+
+// The unqualified names are the D3Q19 set (the z-marching and serving kernels
+// are D3Q19 only).
+constexpr int kQ = D3Q19::Q;
+__host__ __device__ constexpr int cx(int q) { return D3Q19::cx(q); }
+__host__ __device__ constexpr int cy(int q) { return D3Q19::cy(q); }
+__host__ __device__ constexpr int cz(int q) { return D3Q19::cz(q); }
+__host__ __device__ constexpr double wq(int q) { return D3Q19::w(q); }
 
 // symmetric 3x3 storage (xx, xy, xz, yy, yz, zz)
 __host__ __device__ constexpr int sidx(int i, int j)
@@ -348,14 +379,14 @@ __device__ __forceinline__ void bm_flux(double alpha, const double g[6], const d
 
 // c_q . F for the three flux components of one K pair (only the non-zero
 // velocity components enter; each direction has at most two).
-template <int q>
+template <int q, class L = D3Q19>
 __device__ __forceinline__ double cdot(double F0, double F1, double F2)
 {
     double s = 0.0;
     bool first = true;
-    if (cx(q) != 0) { s = cx(q) > 0 ? F0 : -F0; first = false; }
-    if (cy(q) != 0) { s = first ? (cy(q) > 0 ? F1 : -F1) : (cy(q) > 0 ? s + F1 : s - F1); first = false; }
-    if (cz(q) != 0) { s = first ? (cz(q) > 0 ? F2 : -F2) : (cz(q) > 0 ? s + F2 : s - F2); first = false; }
+    if (L::cx(q) != 0) { s = L::cx(q) > 0 ? F0 : -F0; first = false; }
+    if (L::cy(q) != 0) { s = first ? (L::cy(q) > 0 ? F1 : -F1) : (L::cy(q) > 0 ? s + F1 : s - F1); first = false; }
+    if (L::cz(q) != 0) { s = first ? (L::cz(q) > 0 ? F2 : -F2) : (L::cz(q) > 0 ? s + F2 : s - F2); first = false; }
     return s;
 }
 

@@ -9,7 +9,7 @@
 //   d*_q = d_q - omega (d_q - d^eq_q) + w_q (1 - omega/2) R,
 //   d^eq_q = w_q (u - u_rest)                  (alpha, gamma, V)
 //          = w_q ((K - 0) + c_q . F / c_s^2)    (K).
-// Storage layout and the two-launch step are those of the FP64 form.
+// Storage layout, lattices and the two-launch step are those of the FP64 form.
 #include <hip/hip_runtime.h>
 
 #include "lb_device.h"
@@ -19,47 +19,52 @@
 
 namespace lbnr {
 
+template <class L>
 __global__ void __launch_bounds__(256) k_moments32(const float *__restrict__ fin, Geom G, int harmonic,
                                                    double *__restrict__ ubar, double *__restrict__ lm)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) moments_site32(fin, G, s, harmonic, ubar, lm);
+    if (s < G.nsite) moments_site32<L>(fin, G, s, harmonic, ubar, lm);
 }
 
+template <class L>
 __global__ void __launch_bounds__(256) k_collide32(const float *__restrict__ fin, float *__restrict__ fout, Geom G,
                                                    int harmonic, double omega, double srcfac,
                                                    const double *__restrict__ ubar, const double *__restrict__ lm)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) collide_site32(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm);
+    if (s < G.nsite) collide_site32<L>(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm);
 }
 
 // initial deviations: d_q = f^eq_q(u0) - w_q R(u0)/2 - w_q u_rest (FP64, then rounded)
-template <int Fld>
-__device__ __forceinline__ void init32_field(float *__restrict__ fout, const Geom &G, const Site &o, const Params &P)
+template <int Fld, class L>
+__device__ __forceinline__ void init32_field(float *__restrict__ fout, const Geom &G, const SiteT<L> &o,
+                                             const Params &P)
 {
     constexpr bool isK = (Fld >= 7 && Fld <= 12);
     constexpr int pk = isK ? Fld - 7 : 0;
     const double du = P.u[Fld] - urest(Fld);
     const double hR = 0.5 * P.R[Fld];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
+    for (int q = 0; q < L::Q; ++q) {
         double deq;
         if constexpr (isK) {
-            const double cF = (double)cx(q) * P.F[pk] + (double)cy(q) * P.F[6 + pk] + (double)cz(q) * P.F[12 + pk];
-            deq = wq(q) * (du + 3.0 * cF);
+            const double cF = (double)L::cx(q) * P.F[pk] + (double)L::cy(q) * P.F[6 + pk] +
+                              (double)L::cz(q) * P.F[12 + pk];
+            deq = L::w(q) * (du + 3.0 * cF);
         } else {
-            deq = wq(q) * du;
+            deq = L::w(q) * du;
         }
-        plane(fout, G, Fld, q)[o.src[q]] = (float)(deq - wq(q) * hR);
+        plane<L>(fout, G, Fld, q)[o.src[q]] = (float)(deq - L::w(q) * hR);
     }
     if constexpr (Fld + 1 < kFields) init32_field<Fld + 1>(fout, G, o, P);
 }
 
+template <class L>
 __global__ void __launch_bounds__(256) k_init32(Geom G, int harmonic, const double *__restrict__ u0,
                                                 const double *__restrict__ lm, float *__restrict__ fout)
 {
-    Site o;
+    SiteT<L> o;
     if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
     double u[kFields];
 #pragma unroll
@@ -85,30 +90,38 @@ __global__ void __launch_bounds__(256) k_init32(Geom G, int harmonic, const doub
 }
 
 // distributions of one field at the current time, f = w u_rest + d, FP64
+template <class L>
 __global__ void __launch_bounds__(256) k_gather32(const float *__restrict__ fin, Geom G, int F, double *__restrict__ f)
 {
-    Site o;
+    SiteT<L> o;
     if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
     pull_sources(G, o);
     const double ur = urest(F);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q)
-        f[(size_t)q * G.nsite + o.s] = wq(q) * ur + (double)plane(fin, G, F, q)[o.src[q]];
+    for (int q = 0; q < L::Q; ++q)
+        f[(size_t)q * G.nsite + o.s] = L::w(q) * ur + (double)plane<L>(fin, G, F, q)[o.src[q]];
 }
 
 static inline dim3 grid32(uint32_t n) { return dim3((n + 255) / 256); }
 
 hipError_t launch_moments32(const float *fin, const Geom &G, int harmonic, double *ubar, double *lm, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_moments32, grid32(G.nsite), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
+    if (G.nq == D2Q9::Q)
+        hipLaunchKernelGGL(k_moments32<D2Q9>, grid32(G.nsite), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
+    else
+        hipLaunchKernelGGL(k_moments32<D3Q19>, grid32(G.nsite), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
     return hipGetLastError();
 }
 
 hipError_t launch_collide32(const float *fin, float *fout, const Geom &G, int harmonic, double omega, double srcfac,
                             const double *ubar, const double *lm, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_collide32, grid32(G.nsite), dim3(256), 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
-                       lm);
+    if (G.nq == D2Q9::Q)
+        hipLaunchKernelGGL(k_collide32<D2Q9>, grid32(G.nsite), dim3(256), 0, st, fin, fout, G, harmonic, omega,
+                           srcfac, ubar, lm);
+    else
+        hipLaunchKernelGGL(k_collide32<D3Q19>, grid32(G.nsite), dim3(256), 0, st, fin, fout, G, harmonic, omega,
+                           srcfac, ubar, lm);
     return hipGetLastError();
 }
 
@@ -116,13 +129,19 @@ hipError_t launch_init32(const Geom &G, int harmonic, const double *u0, double *
 {
     hipError_t e = launch_copy_lm(G, u0, lm, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_init32, grid32(G.nsite), dim3(256), 0, st, G, harmonic, u0, lm, fout);
+    if (G.nq == D2Q9::Q)
+        hipLaunchKernelGGL(k_init32<D2Q9>, grid32(G.nsite), dim3(256), 0, st, G, harmonic, u0, lm, fout);
+    else
+        hipLaunchKernelGGL(k_init32<D3Q19>, grid32(G.nsite), dim3(256), 0, st, G, harmonic, u0, lm, fout);
     return hipGetLastError();
 }
 
 hipError_t launch_gather32(const float *fin, const Geom &G, int field, double *f, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gather32, grid32(G.nsite), dim3(256), 0, st, fin, G, field, f);
+    if (G.nq == D2Q9::Q)
+        hipLaunchKernelGGL(k_gather32<D2Q9>, grid32(G.nsite), dim3(256), 0, st, fin, G, field, f);
+    else
+        hipLaunchKernelGGL(k_gather32<D3Q19>, grid32(G.nsite), dim3(256), 0, st, fin, G, field, f);
     return hipGetLastError();
 }
 

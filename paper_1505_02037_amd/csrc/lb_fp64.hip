@@ -1,7 +1,8 @@
 // lb_fp64.hip -- FP64 kernels of the Bona-Masso lattice Boltzmann step.
 //
 // Storage (pull scheme).  A distribution buffer holds the post-collision
-// values f*_{F,q}(x) of the previous step, SoA [field][q][plane], one plane of
+// values f*_{F,q}(x) of the previous step, SoA [field][q][plane] (q over the
+// 19 directions of D3Q19 or the 9 of D2Q9), one plane of
 // `ps` doubles per (field, direction) with x fastest (ps = nsite rounded up to
 // 64 elements, so every plane starts 512-byte aligned).  The distribution at
 // the current time is f_{F,q}(x) = buf[F][q][x - c_q] (periodic wrap).
@@ -27,22 +28,24 @@ namespace lbnr {
 // ---------------------------------------------------------------------------
 // k_moments: zeroth moments of all fields and the corrected lapse/metric
 // ---------------------------------------------------------------------------
+template <class L>
 __global__ void __launch_bounds__(256) k_moments(const double *__restrict__ fin, Geom G, int harmonic,
                                                  double *__restrict__ ubar, double *__restrict__ lm)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) moments_site64(fin, G, s, harmonic, ubar, lm);
+    if (s < G.nsite) moments_site64<L>(fin, G, s, harmonic, ubar, lm);
 }
 
 // ---------------------------------------------------------------------------
 // k_collide: sources, flux, BGK relaxation with source, pull streaming
 // ---------------------------------------------------------------------------
+template <class L>
 __global__ void __launch_bounds__(256) k_collide(const double *__restrict__ fin, double *__restrict__ fout,
                                                  Geom G, int harmonic, double omega, double srcfac,
                                                  const double *__restrict__ ubar, const double *__restrict__ lm)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) collide_site64(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm);
+    if (s < G.nsite) collide_site64<L>(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm);
 }
 
 // ---------------------------------------------------------------------------
@@ -74,42 +77,29 @@ __global__ void __launch_bounds__(256) k_init_lm(Geom G, const double *__restric
     for (int F = 0; F < 7; ++F) lm[(size_t)F * G.ps + o.s] = u0[(size_t)F * G.nsite + o.s];
 }
 
-template <int Fld>
-__device__ __forceinline__ void init_field(double *__restrict__ fout, const Geom &G, const Site &o,
+// f_q = f^eq_q - w_q R/2 for one field, direction q fixed at compile time;
+// the pull of direction q at x reads position x - c_q
+template <class L, int Fld, int q = 0>
+__device__ __forceinline__ void init_field_q(double *__restrict__ fout, const Geom &G, const SiteT<L> &o,
+                                             const Params &P, double hR)
+{
+    plane<L>(fout, G, Fld, q)[o.src[q]] = feq64<L, Fld, q>(P) - L::w(q) * hR;
+    if constexpr (q + 1 < L::Q) init_field_q<L, Fld, q + 1>(fout, G, o, P, hR);
+}
+
+template <int Fld, class L>
+__device__ __forceinline__ void init_field(double *__restrict__ fout, const Geom &G, const SiteT<L> &o,
                                            const Params &P)
 {
-    const double u = P.u[Fld];
-    const double hR = 0.5 * P.R[Fld];
-    constexpr bool isK = (Fld >= 7 && Fld <= 12);
-    constexpr int pk = isK ? Fld - 7 : 0;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-        double feq;
-        if constexpr (isK) {
-            double cF;
-            switch (q) {
-#define LBNR_CASE(Q_) case Q_: cF = cdot<Q_>(P.F[pk], P.F[6 + pk], P.F[12 + pk]); break;
-                LBNR_CASE(0) LBNR_CASE(1) LBNR_CASE(2) LBNR_CASE(3) LBNR_CASE(4) LBNR_CASE(5)
-                LBNR_CASE(6) LBNR_CASE(7) LBNR_CASE(8) LBNR_CASE(9) LBNR_CASE(10) LBNR_CASE(11)
-                LBNR_CASE(12) LBNR_CASE(13) LBNR_CASE(14) LBNR_CASE(15) LBNR_CASE(16) LBNR_CASE(17)
-                LBNR_CASE(18)
-#undef LBNR_CASE
-            default: cF = 0.0;
-            }
-            feq = wq(q) * (u + 3.0 * cF);
-        } else {
-            feq = wq(q) * u;
-        }
-        // the pull of direction q at x reads position x - c_q
-        plane(fout, G, Fld, q)[o.src[q]] = feq - wq(q) * hR;
-    }
+    init_field_q<L, Fld>(fout, G, o, P, 0.5 * P.R[Fld]);
     if constexpr (Fld + 1 < kFields) init_field<Fld + 1>(fout, G, o, P);
 }
 
+template <class L>
 __global__ void __launch_bounds__(256) k_init(Geom G, int harmonic, const double *__restrict__ u0,
                                               const double *__restrict__ lm, double *__restrict__ fout)
 {
-    Site o;
+    SiteT<L> o;
     if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
     double u[kFields];
 #pragma unroll
@@ -137,16 +127,17 @@ __global__ void __launch_bounds__(256) k_init(Geom G, int harmonic, const double
 }
 
 // distributions at the current time (after streaming), unpadded
+template <class L>
 __global__ void __launch_bounds__(256) k_gather(const double *__restrict__ fin, Geom G, double *__restrict__ f)
 {
-    Site o;
+    SiteT<L> o;
     if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
     pull_sources(G, o);
 #pragma unroll
     for (int F = 0; F < kFields; ++F)
 #pragma unroll
-        for (int q = 0; q < kQ; ++q)
-            f[((size_t)F * kQ + q) * G.nsite + o.s] = plane(fin, G, F, q)[o.src[q]];
+        for (int q = 0; q < L::Q; ++q)
+            f[((size_t)F * L::Q + q) * G.nsite + o.s] = plane<L>(fin, G, F, q)[o.src[q]];
 }
 
 // ---------------------------------------------------------------------------
@@ -217,15 +208,22 @@ static inline dim3 grid_for(uint32_t n, int threads) { return dim3((n + threads 
 
 hipError_t launch_moments(const double *fin, const Geom &G, int harmonic, double *ubar, double *lm, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_moments, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
+    if (G.nq == D2Q9::Q)
+        hipLaunchKernelGGL(k_moments<D2Q9>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
+    else
+        hipLaunchKernelGGL(k_moments<D3Q19>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
     return hipGetLastError();
 }
 
 hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int harmonic, double omega,
                           double srcfac, const double *ubar, const double *lm, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_collide, grid_for(G.nsite, 256), dim3(256), 0, st, fin, fout, G, harmonic, omega,
-                       srcfac, ubar, lm);
+    if (G.nq == D2Q9::Q)
+        hipLaunchKernelGGL(k_collide<D2Q9>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, fout, G, harmonic, omega,
+                           srcfac, ubar, lm);
+    else
+        hipLaunchKernelGGL(k_collide<D3Q19>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, fout, G, harmonic, omega,
+                           srcfac, ubar, lm);
     return hipGetLastError();
 }
 
@@ -245,13 +243,19 @@ hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm
 {
     hipError_t e = launch_copy_lm(G, u0, lm, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_init, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, u0, lm, fout);
+    if (G.nq == D2Q9::Q)
+        hipLaunchKernelGGL(k_init<D2Q9>, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, u0, lm, fout);
+    else
+        hipLaunchKernelGGL(k_init<D3Q19>, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, u0, lm, fout);
     return hipGetLastError();
 }
 
 hipError_t launch_gather(const double *fin, const Geom &G, double *f, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gather, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, f);
+    if (G.nq == D2Q9::Q)
+        hipLaunchKernelGGL(k_gather<D2Q9>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, f);
+    else
+        hipLaunchKernelGGL(k_gather<D3Q19>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, f);
     return hipGetLastError();
 }
 

@@ -12,9 +12,11 @@ struct Geom {
     int nx, ny, nz;
     uint32_t nsite;  // nx * ny * nz
     size_t ps;       // plane stride in elements (nsite rounded up to 64)
+    int nq = 19;     // directions of the lattice: 19 (D3Q19) or 9 (D2Q9, nz = 1)
 };
 
-// FP64 form (lb_fp64.hip)
+// FP64 form (lb_fp64.hip); the split-step launchers, the initialisation and
+// the gather run the lattice G.nq names
 hipError_t launch_moments(const double *fin, const Geom &G, int harmonic, double *ubar, double *lm, hipStream_t st);
 hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int harmonic, double omega,
                           double srcfac, const double *ubar, const double *lm, hipStream_t st);

@@ -1,5 +1,6 @@
 // lb_site.h -- site indexing and pull addressing shared by the kernels
-// (periodic lattice, x fastest, one plane of `ps` elements per (field, q)).
+// (periodic lattice, x fastest, one plane of `ps` elements per (field, q)),
+// for a lattice L (D3Q19 or D2Q9).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,13 +11,16 @@
 
 namespace lbnr {
 
-struct Site {
+template <class L>
+struct SiteT {
     int x, y, z;
     uint32_t s;                // site index
-    uint32_t src[kQ];          // index of x - c_q (periodic)
+    uint32_t src[L::Q];        // index of x - c_q (periodic)
 };
+using Site = SiteT<D3Q19>;
 
-__device__ __forceinline__ bool site_of(const Geom &G, uint32_t s, Site &o)
+template <class L>
+__device__ __forceinline__ bool site_of(const Geom &G, uint32_t s, SiteT<L> &o)
 {
     if (s >= G.nsite) return false;
     o.s = s;
@@ -37,20 +41,22 @@ __device__ __forceinline__ uint32_t neighbour(const Geom &G, int x, int y, int z
     return ((uint32_t)zz * (uint32_t)G.ny + (uint32_t)yy) * (uint32_t)G.nx + (uint32_t)xx;
 }
 
-__device__ __forceinline__ void pull_sources(const Geom &G, Site &o)
+template <class L>
+__device__ __forceinline__ void pull_sources(const Geom &G, SiteT<L> &o)
 {
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) o.src[q] = neighbour(G, o.x, o.y, o.z, -cx(q), -cy(q), -cz(q));
+    for (int q = 0; q < L::Q; ++q) o.src[q] = neighbour(G, o.x, o.y, o.z, -L::cx(q), -L::cy(q), -L::cz(q));
 }
 
-template <typename T>
+template <class L = D3Q19, typename T>
 __device__ __forceinline__ T *plane(T *buf, const Geom &G, int F, int q)
 {
-    return buf + ((size_t)F * kQ + (size_t)q) * G.ps;
+    return buf + ((size_t)F * L::Q + (size_t)q) * G.ps;
 }
 
 // A_k and D_kij at a site from the corrected lapse/metric of its neighbours
-__device__ __forceinline__ void stencil(const Geom &G, const Site &o, const double *__restrict__ lm,
+template <class L>
+__device__ __forceinline__ void stencil(const Geom &G, const SiteT<L> &o, const double *__restrict__ lm,
                                         double alpha, double A[3], double D[18])
 {
 #pragma unroll
@@ -103,7 +109,8 @@ __device__ __forceinline__ void params_from(const double ub[kFields], const doub
     bm_flux(alpha, c + 1, gi, V, A, D, P.F);
 }
 
-__device__ __forceinline__ void site_params(const Geom &G, const Site &o, int harmonic,
+template <class L>
+__device__ __forceinline__ void site_params(const Geom &G, const SiteT<L> &o, int harmonic,
                                             const double ub[kFields], const double *__restrict__ lm,
                                             Params &P)
 {

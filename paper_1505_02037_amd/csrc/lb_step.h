@@ -11,22 +11,23 @@
 
 namespace lbnr {
 
-// Zeroth moment of field F at a site from its 19 pulled distributions, summed
+// Zeroth moment of field F at a site from its pulled distributions, summed
 // plane by plane: the in-plane directions (c_z = 0), those arriving from the
 // plane below (c_z = +1), those from the plane above (c_z = -1), each in
 // direction order, then (in-plane + below) + above.  The z-marching kernel
 // forms the three partial sums in different iterations; every other kernel
-// uses the same grouping so that all paths agree bit for bit.
-template <typename T>
-__device__ __forceinline__ double plane_sum(const T *__restrict__ fin, const Geom &G, int F, const Site &o)
+// uses the same grouping so that all paths agree bit for bit.  (On D2Q9 both
+// out-of-plane sums are empty.)
+template <typename T, class L>
+__device__ __forceinline__ double plane_sum(const T *__restrict__ fin, const Geom &G, int F, const SiteT<L> &o)
 {
     double in_plane = 0.0, below = 0.0, above = 0.0;
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-        const double f = (double)plane(fin, G, F, q)[o.src[q]];
-        if (cz(q) == 0)
+    for (int q = 0; q < L::Q; ++q) {
+        const double f = (double)plane<L>(fin, G, F, q)[o.src[q]];
+        if (L::cz(q) == 0)
             in_plane += f;
-        else if (cz(q) > 0)
+        else if (L::cz(q) > 0)
             below += f;
         else
             above += f;
@@ -39,10 +40,11 @@ __device__ __forceinline__ double plane_sum(const T *__restrict__ fin, const Geo
 // ---------------------------------------------------------------------------
 
 // zeroth moments of all fields at site s and its corrected lapse/metric
+template <class L = D3Q19>
 __device__ __forceinline__ void moments_site64(const double *__restrict__ fin, const Geom &G, uint32_t s,
                                                int harmonic, double *__restrict__ ubar, double *__restrict__ lm)
 {
-    Site o;
+    SiteT<L> o;
     site_of(G, s, o);
     pull_sources(G, o);
     double ub[kFields];
@@ -58,57 +60,57 @@ __device__ __forceinline__ void moments_site64(const double *__restrict__ fin, c
     for (int F = 0; F < 7; ++F) lm[(size_t)F * G.ps + o.s] = c[F];
 }
 
-// post-collision values of one field's 19 distributions (Eq. numlb with the
-// equilibria and sources of the field): out_q = f_q - omega (f_q - feq_q) + S_q
-template <int Fld>
-__device__ __forceinline__ void relax64(const double fl[kQ], const Params &P, double omega, double srcfac,
-                                        double out[kQ])
+// equilibrium of field Fld in direction q (Eqs. alfa..ekst, zero shift):
+// w_q u for the lapse, metric and V; w_q (u + c_q.F / c_s^2) for K
+template <class L, int Fld, int q>
+__device__ __forceinline__ double feq64(const Params &P)
 {
-    const double u = P.u[Fld];
-    const double hR = srcfac * P.R[Fld];
     constexpr bool isK = (Fld >= 7 && Fld <= 12);
     constexpr int pk = isK ? Fld - 7 : 0;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-        double feq;
-        if constexpr (isK) {
-            double cF;
-            switch (q) {
-#define LBNR_CASE(Q_) case Q_: cF = cdot<Q_>(P.F[pk], P.F[6 + pk], P.F[12 + pk]); break;
-                LBNR_CASE(0) LBNR_CASE(1) LBNR_CASE(2) LBNR_CASE(3) LBNR_CASE(4) LBNR_CASE(5)
-                LBNR_CASE(6) LBNR_CASE(7) LBNR_CASE(8) LBNR_CASE(9) LBNR_CASE(10) LBNR_CASE(11)
-                LBNR_CASE(12) LBNR_CASE(13) LBNR_CASE(14) LBNR_CASE(15) LBNR_CASE(16) LBNR_CASE(17)
-                LBNR_CASE(18)
-#undef LBNR_CASE
-            default: cF = 0.0;
-            }
-            feq = wq(q) * (u + 3.0 * cF);
-        } else {
-            feq = wq(q) * u;
-        }
-        const double f = fl[q];
-        out[q] = f - omega * (f - feq) + wq(q) * hR;
-    }
+    const double u = P.u[Fld];
+    if constexpr (isK)
+        return L::w(q) * (u + 3.0 * cdot<q, L>(P.F[pk], P.F[6 + pk], P.F[12 + pk]));
+    else
+        return L::w(q) * u;
 }
 
-// relax one field's 19 distributions and store them at x
-template <int Fld>
+// post-collision values of one field's distributions (Eq. numlb with the
+// equilibria and sources of the field): out_q = f_q - omega (f_q - feq_q) + S_q,
+// direction q fixed at compile time
+template <class L, int Fld, int q = 0>
+__device__ __forceinline__ void relax64_q(const double *fl, const Params &P, double omega, double hR, double *out)
+{
+    const double feq = feq64<L, Fld, q>(P);
+    const double f = fl[q];
+    out[q] = f - omega * (f - feq) + L::w(q) * hR;
+    if constexpr (q + 1 < L::Q) relax64_q<L, Fld, q + 1>(fl, P, omega, hR, out);
+}
+
+template <int Fld, class L = D3Q19>
+__device__ __forceinline__ void relax64(const double fl[L::Q], const Params &P, double omega, double srcfac,
+                                        double out[L::Q])
+{
+    relax64_q<L, Fld>(fl, P, omega, srcfac * P.R[Fld], out);
+}
+
+// relax one field's distributions and store them at x
+template <int Fld, class L>
 __device__ __forceinline__ void collide_field(const double *__restrict__ fin, double *__restrict__ fout,
-                                              const Geom &G, const Site &o, const Params &P,
+                                              const Geom &G, const SiteT<L> &o, const Params &P,
                                               double omega, double srcfac)
 {
-    double fl[kQ], out[kQ];
+    double fl[L::Q], out[L::Q];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) fl[q] = plane(fin, G, Fld, q)[o.src[q]];
-    relax64<Fld>(fl, P, omega, srcfac, out);
+    for (int q = 0; q < L::Q; ++q) fl[q] = plane<L>(fin, G, Fld, q)[o.src[q]];
+    relax64<Fld, L>(fl, P, omega, srcfac, out);
     // streamed: read again only by the next step's pulls
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(out[q], &plane(fout, G, Fld, q)[o.s]);
+    for (int q = 0; q < L::Q; ++q) __builtin_nontemporal_store(out[q], &plane<L>(fout, G, Fld, q)[o.s]);
 }
 
-template <int Fld>
+template <int Fld, class L>
 __device__ __forceinline__ void collide_all(const double *__restrict__ fin, double *__restrict__ fout,
-                                            const Geom &G, const Site &o, const Params &P,
+                                            const Geom &G, const SiteT<L> &o, const Params &P,
                                             double omega, double srcfac)
 {
     collide_field<Fld>(fin, fout, G, o, P, omega, srcfac);
@@ -116,12 +118,13 @@ __device__ __forceinline__ void collide_all(const double *__restrict__ fin, doub
 }
 
 // sources, flux, BGK relaxation with source and pull streaming at site s
+template <class L = D3Q19>
 __device__ __forceinline__ void collide_site64(const double *__restrict__ fin, double *__restrict__ fout,
                                                const Geom &G, uint32_t s, int harmonic, double omega,
                                                double srcfac, const double *__restrict__ ubar,
                                                const double *__restrict__ lm)
 {
-    Site o;
+    SiteT<L> o;
     site_of(G, s, o);
     double ub[kFields];
 #pragma unroll
@@ -137,12 +140,14 @@ __device__ __forceinline__ void collide_site64(const double *__restrict__ fin, d
 // ---------------------------------------------------------------------------
 
 __host__ __device__ constexpr double urest(int F) { return (F == 0 || F == 1 || F == 4 || F == 6) ? 1.0 : 0.0; }
-__host__ __device__ constexpr float wqf(int q) { return (float)wq(q); }
+template <class L = D3Q19>
+__host__ __device__ constexpr float wqf(int q) { return (float)L::w(q); }
 
+template <class L = D3Q19>
 __device__ __forceinline__ void moments_site32(const float *__restrict__ fin, const Geom &G, uint32_t s,
                                                int harmonic, double *__restrict__ ubar, double *__restrict__ lm)
 {
-    Site o;
+    SiteT<L> o;
     site_of(G, s, o);
     pull_sources(G, o);
     double ub[kFields];
@@ -158,20 +163,35 @@ __device__ __forceinline__ void moments_site32(const float *__restrict__ fin, co
     for (int F = 0; F < 7; ++F) lm[(size_t)F * G.ps + o.s] = c[F];
 }
 
-template <int q>
+template <int q, class L>
 __device__ __forceinline__ float cdotf(float F0, float F1, float F2)
 {
     float s = 0.0f;
-    if (cx(q) != 0) s += cx(q) > 0 ? F0 : -F0;
-    if (cy(q) != 0) s += cy(q) > 0 ? F1 : -F1;
-    if (cz(q) != 0) s += cz(q) > 0 ? F2 : -F2;
+    if (L::cx(q) != 0) s += L::cx(q) > 0 ? F0 : -F0;
+    if (L::cy(q) != 0) s += L::cy(q) > 0 ? F1 : -F1;
+    if (L::cz(q) != 0) s += L::cz(q) > 0 ? F2 : -F2;
     return s;
 }
 
-// post-collision deviations of one field's 19 distributions, in FP32:
-// out_q = d_q - omega (d_q - d^eq_q) + w_q (1 - omega/2) R
-template <int Fld>
-__device__ __forceinline__ void relax32(const float fl[kQ], const Params &P, float om, double srcfac, float out[kQ])
+// post-collision deviations of one field's distributions, in FP32:
+// out_q = d_q - omega (d_q - d^eq_q) + w_q (1 - omega/2) R, q fixed at compile time
+template <class L, bool isK, int q = 0>
+__device__ __forceinline__ void relax32_q(const float *fl, float du, float hR, float F0, float F1, float F2, float om,
+                                          float *out)
+{
+    float deq;
+    if constexpr (isK)
+        deq = wqf<L>(q) * (du + 3.0f * cdotf<q, L>(F0, F1, F2));
+    else
+        deq = wqf<L>(q) * du;
+    const float d = fl[q];
+    out[q] = d - om * (d - deq) + wqf<L>(q) * hR;
+    if constexpr (q + 1 < L::Q) relax32_q<L, isK, q + 1>(fl, du, hR, F0, F1, F2, om, out);
+}
+
+template <int Fld, class L = D3Q19>
+__device__ __forceinline__ void relax32(const float fl[L::Q], const Params &P, float om, double srcfac,
+                                        float out[L::Q])
 {
     constexpr bool isK = (Fld >= 7 && Fld <= 12);
     constexpr int pk = isK ? Fld - 7 : 0;
@@ -180,48 +200,29 @@ __device__ __forceinline__ void relax32(const float fl[kQ], const Params &P, flo
     const float F0 = isK ? (float)P.F[pk] : 0.0f;
     const float F1 = isK ? (float)P.F[6 + pk] : 0.0f;
     const float F2 = isK ? (float)P.F[12 + pk] : 0.0f;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-        float deq;
-        if constexpr (isK) {
-            float cF;
-            switch (q) {
-#define LBNR_CASE(Q_) case Q_: cF = cdotf<Q_>(F0, F1, F2); break;
-                LBNR_CASE(0) LBNR_CASE(1) LBNR_CASE(2) LBNR_CASE(3) LBNR_CASE(4) LBNR_CASE(5)
-                LBNR_CASE(6) LBNR_CASE(7) LBNR_CASE(8) LBNR_CASE(9) LBNR_CASE(10) LBNR_CASE(11)
-                LBNR_CASE(12) LBNR_CASE(13) LBNR_CASE(14) LBNR_CASE(15) LBNR_CASE(16) LBNR_CASE(17)
-                LBNR_CASE(18)
-#undef LBNR_CASE
-            default: cF = 0.0f;
-            }
-            deq = wqf(q) * (du + 3.0f * cF);
-        } else {
-            deq = wqf(q) * du;
-        }
-        const float d = fl[q];
-        out[q] = d - om * (d - deq) + wqf(q) * hR;
-    }
+    relax32_q<L, isK>(fl, du, hR, F0, F1, F2, om, out);
 }
 
-template <int Fld>
+template <int Fld, class L>
 __device__ __forceinline__ void collide32_all(const float *__restrict__ fin, float *__restrict__ fout, const Geom &G,
-                                              const Site &o, const Params &P, float om, double srcfac)
+                                              const SiteT<L> &o, const Params &P, float om, double srcfac)
 {
-    float fl[kQ], out[kQ];
+    float fl[L::Q], out[L::Q];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) fl[q] = plane(fin, G, Fld, q)[o.src[q]];
-    relax32<Fld>(fl, P, om, srcfac, out);
+    for (int q = 0; q < L::Q; ++q) fl[q] = plane<L>(fin, G, Fld, q)[o.src[q]];
+    relax32<Fld, L>(fl, P, om, srcfac, out);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(out[q], &plane(fout, G, Fld, q)[o.s]);
+    for (int q = 0; q < L::Q; ++q) __builtin_nontemporal_store(out[q], &plane<L>(fout, G, Fld, q)[o.s]);
     if constexpr (Fld + 1 < kFields) collide32_all<Fld + 1>(fin, fout, G, o, P, om, srcfac);
 }
 
+template <class L = D3Q19>
 __device__ __forceinline__ void collide_site32(const float *__restrict__ fin, float *__restrict__ fout,
                                                const Geom &G, uint32_t s, int harmonic, double omega,
                                                double srcfac, const double *__restrict__ ubar,
                                                const double *__restrict__ lm)
 {
-    Site o;
+    SiteT<L> o;
     site_of(G, s, o);
     double ub[kFields];
 #pragma unroll

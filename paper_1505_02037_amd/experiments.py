@@ -14,6 +14,7 @@ for bit, as the parity tests show).
   lin  linear (gravitational) wave at the paper's setup: 800 sites per
        wavelength, A = 1e-5, tau = 4.5, geodesic slicing, D3Q19
   gw   gauge wave at the paper's setup: 800 sites, A = 1e-3, tau = 4.5
+  q9   D2Q9: the paper's gauge wave on its lattice, and 4096^2 throughput
 
 Error measures (per field, group-scaled): max |u - ref| over the lattice,
 divided by the max-norm of the field's tensor in ref (alpha alone, gamma, K
@@ -242,12 +243,12 @@ def c5(margin_gib: float = 3.0):
     return out
 
 
-def _paper_wave(name, make, field, slicing, A, tau=4.5, n=800, steps=3000):
+def _paper_wave(name, make, field, slicing, A, tau=4.5, n=800, steps=3000, lattice=lb.D3Q19):
     """Error of `field` against its analytic wave every 100 steps and the
     step at which its deviation-relative error first exceeds 10 %."""
     torch = _torch()
-    out = {"experiment": name, "N": n, "A": A, "tau": tau, "checks": []}
-    with lb.Lattice(n, 1, 1, tau, slicing=slicing, device=0) as g:
+    out = {"experiment": name, "N": n, "A": A, "tau": tau, "lattice": lattice, "checks": []}
+    with lb.Lattice(n, 1, 1, tau, slicing=slicing, device=0, lattice=lattice) as g:
         g.init_fields(make(n, 1, 1, A, float(n)))
         life = None
         u = torch.empty((16, 1, 1, n), dtype=torch.float64, device="cuda")
@@ -278,10 +279,38 @@ def gw():
     return _paper_wave("gw gauge wave, paper setup", workloads.gauge_wave_x, 1, lb.HARMONIC, 1e-3)
 
 
+def q9():
+    """D2Q9: the paper's gauge wave on its own lattice, and the throughput of
+    the D2Q9 step on a 4096 x 4096 lattice ((1,1,0) wave, tau = 0.6) in both
+    storage forms."""
+    import workloads
+
+    torch = _torch()
+    out = {"experiment": "q9 D2Q9", "paper_gauge_wave": _paper_wave(
+        "gauge wave, paper setup, D2Q9", workloads.gauge_wave_x, 1, lb.HARMONIC, 1e-3, lattice=lb.D2Q9)}
+    out["paper_gauge_wave"].pop("checks")
+    n, tau, steps = 4096, 0.6, 20
+    u0 = torch.from_numpy(workloads.gauge_wave_diag(n, 1, 0.1)).cuda()
+    for form, prec, bps in (("fp64", lb.FP64, 2 * 16 * 9 * 8), ("fp32", lb.FP32_DEV, 2 * 16 * 9 * 4)):
+        with lb.Lattice(n, n, 1, tau, precision=prec, device=0, lattice=lb.D2Q9) as g:
+            g.init_fields(u0)
+            g.step(3)
+            torch.cuda.synchronize()
+            g.set_timing(True)
+            t0 = time.perf_counter()
+            g.step(steps)
+            wall = time.perf_counter() - t0
+            kt = g.kernel_times()
+        out[form] = {"lattice": [n, n, 1], "steps": steps, "ms_per_step": 1000 * wall / steps,
+                     "field_site_updates_per_s": 16 * n * n * steps / wall, "kernel_ms": kt,
+                     "algorithmic_GBps": bps * n * n / (sum(kt.values()) * 1e-3) / 1e9}
+    return out
+
+
 def main(argv=None) -> int:
     which = (argv if argv is not None else sys.argv[1:]) or ["c1"]
     for w in which:
-        res = {"c1": c1, "c2": c2, "c2s": c2s, "c3": c3, "c5": c5, "lin": lin, "gw": gw}[w]()
+        res = {"c1": c1, "c2": c2, "c2s": c2s, "c3": c3, "c5": c5, "lin": lin, "gw": gw, "q9": q9}[w]()
         print(json.dumps(res), flush=True)
     return 0
 

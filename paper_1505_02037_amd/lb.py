@@ -24,6 +24,9 @@ LB_ENOMEM = -2
 LB_EDEVICE = -3
 LB_ESTATE = -4
 LB_D3Q19 = 19
+LB_D2Q9 = 9
+D3Q19 = LB_D3Q19
+D2Q9 = LB_D2Q9
 HARMONIC = 0
 GEODESIC = 1
 FP64 = 0
@@ -127,13 +130,13 @@ def _ptr(a, nelem: int):
 
 
 def make_config(nx, ny, nz, tau, slicing=HARMONIC, precision=FP64, device=-1, stream=None,
-                path=PATH_AUTO) -> LBConfig:
-    return LBConfig(LB_D3Q19, int(nx), int(ny), int(nz), float(tau), int(slicing), int(precision),
+                path=PATH_AUTO, lattice=LB_D3Q19) -> LBConfig:
+    return LBConfig(int(lattice), int(nx), int(ny), int(nz), float(tau), int(slicing), int(precision),
                     int(device), ctypes.c_void_p(stream) if stream else None, int(path))
 
 
-def device_bytes(nx, ny, nz, tau=0.6, precision=FP64) -> int:
-    cfg = make_config(nx, ny, nz, tau, precision=precision)
+def device_bytes(nx, ny, nz, tau=0.6, precision=FP64, lattice=LB_D3Q19, path=PATH_AUTO) -> int:
+    cfg = make_config(nx, ny, nz, tau, precision=precision, lattice=lattice, path=path)
     return int(load_library().lb_device_bytes(ctypes.byref(cfg)))
 
 
@@ -141,12 +144,14 @@ class Lattice:
     """One periodic lattice evolved on the GPU (lb_create ... lb_destroy)."""
 
     def __init__(self, nx: int, ny: int, nz: int, tau: float, slicing: int = HARMONIC,
-                 precision: int = FP64, device: int = -1, stream=None, path: int = PATH_AUTO):
+                 precision: int = FP64, device: int = -1, stream=None, path: int = PATH_AUTO,
+                 lattice: int = LB_D3Q19):
         lib = load_library()
         self._lib = lib
         self.shape = (nz, ny, nx)
         self.nsite = nx * ny * nz
-        cfg = make_config(nx, ny, nz, tau, slicing, precision, device, stream, path)
+        self.nq = int(lattice)
+        cfg = make_config(nx, ny, nz, tau, slicing, precision, device, stream, path, lattice)
         h = ctypes.c_void_p()
         _check(lib.lb_create(ctypes.byref(cfg), ctypes.byref(h)), "lb_create")
         self._h = h
@@ -184,8 +189,8 @@ class Lattice:
 
     def distributions(self, out=None):
         if out is None:
-            out = np.empty((NF, NQ) + self.shape, dtype=np.float64)
-        p, dev = _ptr(out, NF * NQ * self.nsite)
+            out = np.empty((NF, self.nq) + self.shape, dtype=np.float64)
+        p, dev = _ptr(out, NF * self.nq * self.nsite)
         _check(self._lib.lb_get_distributions(self._h, p, dev), "lb_get_distributions")
         return out
 

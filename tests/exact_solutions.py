@@ -215,3 +215,115 @@ SOLUTIONS = {
     "lemaitre_sheared": lemaitre_sheared,
     "kruskal_sheared": kruskal_sheared,
 }
+
+
+# --------------------------------------------------------------------------
+# spacetimes with matter: every metric solves the Einstein equations with the
+# energy-momentum tensor equal to its Einstein tensor (units c = 8 pi G = 1)
+# --------------------------------------------------------------------------
+
+def flrw(w) -> Solution:
+    """Flat FLRW with a perfect fluid P = w rho, comoving coordinates,
+    alpha = 1: a(t) = t^(2 / (3 (1 + w))), gamma = a^2 delta (section
+    "Expansion of flat universe" has w = 1, gamma = t^(2/3) delta)."""
+    q = sp.Rational(2, 3) / (1 + w)
+    a2 = t ** (2 * q)
+    name = {sp.Integer(1): "flrw_stiff", sp.Integer(0): "flrw_dust"}.get(sp.nsimplify(w), f"flrw_{w}")
+    return Solution(name, sp.Integer(1), a2 * sp.eye(3), sp.eye(3) / a2, "geodesic",
+                    ((1.0, 0.0, 0.0, 0.0), (1.7, 0.3, -0.2, 0.5)))
+
+
+def flrw_stiff_sheared() -> Solution:
+    return _shear_solution(flrw(sp.Integer(1)), "flrw_stiff_sheared", ((1.2, 0.1, 0.2, 0.3),))
+
+
+def flrw_dust_sheared() -> Solution:
+    return _shear_solution(flrw(sp.Integer(0)), "flrw_dust_sheared", ((1.4, -0.5, 0.2, 0.1),))
+
+
+def manufactured() -> Solution:
+    """A generic zero-shift metric (lapse and all six metric components vary
+    in space and time).  Its Einstein tensor is a general energy-momentum
+    tensor: energy density, momentum density G^0_k and anisotropic stresses
+    are all non-zero."""
+    a = 1 + sp.Rational(1, 10) * sp.sin(x1 + 2 * x2 - t / 3) + sp.Rational(1, 20) * sp.cos(x3 - t)
+    h = sp.Matrix([
+        [sp.sin(x1 + t) / 8, sp.cos(x2 - 2 * t) / 15, sp.sin(x3 + x1) / 17],
+        [0, sp.cos(x1 + x3 + t / 2) / 9, sp.sin(x2 - t) / 13],
+        [0, 0, sp.sin(x1 - x2 + x3 + t) / 11],
+    ])
+    g = sp.eye(3) + sp.Matrix(3, 3, lambda i, j: h[min(i, j), max(i, j)])
+    return Solution("manufactured", a, g, g.inv(method="ADJ"), None,
+                    ((0.3, 0.2, -0.4, 0.7), (1.1, -0.9, 0.5, 0.2)))
+
+
+MATTER_SOLUTIONS = {
+    "flrw_stiff": lambda: flrw(sp.Integer(1)),
+    "flrw_dust": lambda: flrw(sp.Integer(0)),
+    "flrw_stiff_sheared": flrw_stiff_sheared,
+    "flrw_dust_sheared": flrw_dust_sheared,
+    "manufactured": manufactured,
+}
+SOLUTIONS.update(MATTER_SOLUTIONS)
+
+
+@functools.lru_cache(maxsize=None)
+def _metric_derivatives(name: str):
+    """Lambdified 4-metric g_ab, its first and second coordinate derivatives
+    (coordinates t, x1, x2, x3; zero shift)."""
+    sol = SOLUTIONS[name]()
+    C = (t, x1, x2, x3)
+    g4 = sp.zeros(4, 4)
+    g4[0, 0] = -sol.alpha ** 2
+    for i in range(3):
+        for j in range(3):
+            g4[1 + i, 1 + j] = sol.gamma[i, j]
+    comps = [(a, b) for a in range(4) for b in range(a, 4)]
+    d1 = [[sp.diff(g4[a, b], C[c]) for (a, b) in comps] for c in range(4)]
+    d2 = [[[sp.diff(g4[a, b], C[c], C[d]) for (a, b) in comps] for d in range(4)] for c in range(4)]
+    f0 = sp.lambdify(C, [g4[a, b] for (a, b) in comps], modules="mpmath")
+    f1 = sp.lambdify(C, d1, modules="mpmath")
+    f2 = sp.lambdify(C, d2, modules="mpmath")
+    return comps, f0, f1, f2
+
+
+def einstein_matter(name: str, point):
+    """The energy-momentum tensor G = Einstein tensor of the solution's
+    4-metric at point, as the 10 components the sources take: G^00, G^0_k,
+    G_ij (xx, xy, xz, yy, yz, zz).  Christoffel symbols and the Ricci tensor
+    are formed from exact metric derivatives in 40-digit arithmetic."""
+    import mpmath
+
+    comps, f0, f1, f2 = _metric_derivatives(name)
+    with mpmath.workdps(40):
+        def full(vals):
+            m = [[mpmath.mpf(0)] * 4 for _ in range(4)]
+            for (a, b), v in zip(comps, vals):
+                m[a][b] = m[b][a] = mpmath.re(v)
+            return m
+
+        g = full(f0(*point))
+        dg = [full(v) for v in f1(*point)]                      # dg[c][a][b]
+        ddg = [[full(v) for v in row] for row in f2(*point)]     # ddg[c][d][a][b]
+        gi_m = mpmath.matrix(g) ** -1
+        gi = [[gi_m[a, b] for b in range(4)] for a in range(4)]
+        R4 = range(4)
+        # d_e g^{ad} = -g^{ap} d_e g_pq g^{qd}
+        dgi = [[[-sum(gi[a][p] * dg[e][p][q] * gi[q][d] for p in R4 for q in R4) for d in R4] for a in R4]
+               for e in R4]
+        # lowered Christoffel [d, bc] and its derivative
+        low = [[[(dg[b][d][c] + dg[c][d][b] - dg[d][b][c]) / 2 for c in R4] for b in R4] for d in R4]
+        dlow = [[[[(ddg[e][b][d][c] + ddg[e][c][d][b] - ddg[e][d][b][c]) / 2 for c in R4] for b in R4]
+                 for d in R4] for e in R4]
+        Gam = [[[sum(gi[a][d] * low[d][b][c] for d in R4) for c in R4] for b in R4] for a in R4]
+        dGam = [[[[sum(dgi[e][a][d] * low[d][b][c] + gi[a][d] * dlow[e][d][b][c] for d in R4) for c in R4]
+                  for b in R4] for a in R4] for e in R4]                 # dGam[e][a][b][c] = d_e Gam^a_bc
+        Ric = [[sum(dGam[a][a][b][d] - dGam[d][a][a][b]
+                    + sum(Gam[a][a][e] * Gam[e][b][d] - Gam[a][d][e] * Gam[e][a][b] for e in R4)
+                    for a in R4) for d in R4] for b in R4]
+        Rs = sum(gi[b][d] * Ric[b][d] for b in R4 for d in R4)
+        Ein = [[Ric[a][b] - g[a][b] * Rs / 2 for b in R4] for a in R4]
+        G00 = sum(gi[0][a] * gi[0][b] * Ein[a][b] for a in R4 for b in R4)
+        G0k = [sum(gi[0][a] * Ein[a][1 + k] for a in R4) for k in range(3)]
+        Gij = [Ein[1 + i][1 + j] for i, j in PAIRS]
+        return np.array([float(v) for v in [G00] + G0k + Gij])

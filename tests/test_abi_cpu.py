@@ -88,6 +88,9 @@ def test_bad_configs_are_rejected_without_a_device(lib):
         lb.make_config(8, 8, 8, 0.6, precision=9),
         lb.make_config(2048, 2048, 2048, 0.6),  # more than 2^32 sites
         lb.make_config(8, 8, 8, 0.6, path=3),
+        lb.make_config(8, 8, 8, 0.6, lattice=7),                      # unknown lattice
+        lb.make_config(8, 8, 2, 0.6, lattice=lb.D2Q9),                # D2Q9 is one site thick
+        lb.make_config(8, 8, 1, 0.6, lattice=lb.D2Q9, path=lb.PATH_FUSED),  # split path only
     ]
     for cfg in bad:
         h = ctypes.c_void_p(1234)
@@ -118,6 +121,11 @@ def test_device_bytes_matches_layout(lib):
     ps = (n + 63) // 64 * 64
     assert lb.device_bytes(100, 30, 7) == (2 * 16 * 19 + 16 + 7) * ps * 8
     assert lb.device_bytes(100, 30, 7, precision=lb.FP32_DEV) == (16 * 19 + 16 + 7) * ps * 8
+    assert lb.device_bytes(100, 30, 7, path=lb.PATH_FUSED) == (2 * 16 * 19 + 16 + 16 + 7) * ps * 8
+    n2 = 100 * 30
+    ps2 = (n2 + 63) // 64 * 64
+    assert lb.device_bytes(100, 30, 1, lattice=lb.D2Q9) == (2 * 16 * 9 + 16 + 7) * ps2 * 8
+    assert lb.device_bytes(100, 30, 1, precision=lb.FP32_DEV, lattice=lb.D2Q9) == (16 * 9 + 16 + 7) * ps2 * 8
 
 
 def test_build_entry_reaches_both_build_steps(monkeypatch):

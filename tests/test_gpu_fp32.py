@@ -41,26 +41,28 @@ def _rel_err(u, ref):
     return num / scale
 
 
-def _fp32(shape, tau, slicing=oracle.HARMONIC):
+def _fp32(shape, tau, slicing=oracle.HARMONIC, lattice=19):
     from paper_1505_02037_amd import lb
 
     nz, ny, nx = shape
-    return lb.Lattice(nx, ny, nz, tau, slicing=slicing, precision=lb.FP32_DEV, device=0)
+    return lb.Lattice(nx, ny, nz, tau, slicing=slicing, precision=lb.FP32_DEV, device=0, lattice=lattice)
 
 
-@pytest.mark.parametrize("shape,tau,slicing,seed,horizons", [
-    ((5, 7, 13), 0.7, oracle.HARMONIC, 1, (0, 1, 5, 10)),
-    ((9, 17, 33), 1.0, oracle.GEODESIC, 2, (0, 1, 10, 30)),
-    ((1, 3, 2), 0.9, oracle.HARMONIC, 3, (0, 2, 10)),
+@pytest.mark.parametrize("shape,tau,slicing,seed,horizons,lattice", [
+    ((5, 7, 13), 0.7, oracle.HARMONIC, 1, (0, 1, 5, 10), 19),
+    ((9, 17, 33), 1.0, oracle.GEODESIC, 2, (0, 1, 10, 30), 19),
+    ((1, 3, 2), 0.9, oracle.HARMONIC, 3, (0, 2, 10), 19),
+    ((1, 29, 37), 0.8, oracle.HARMONIC, 4, (0, 1, 5, 10), 9),
+    ((1, 1, 5), 1.0, oracle.GEODESIC, 5, (0, 2, 10), 9),
 ])
-def test_fp32_random_state_within_bound(shape, tau, slicing, seed, horizons):
+def test_fp32_random_state_within_bound(shape, tau, slicing, seed, horizons, lattice):
     _torch()
     nz, ny, nx = shape
-    print(f"[fp32] random {nx}x{ny}x{nz} tau={tau}", flush=True)
+    print(f"[fp32] random {nx}x{ny}x{nz} tau={tau} lattice=D{2 if lattice == 9 else 3}Q{lattice}", flush=True)
     u0 = workloads.random_state(nx, ny, nz, seed=seed, amp=0.05)
-    o = oracle.Oracle(nx, ny, nz, tau, slicing)
+    o = oracle.Oracle(nx, ny, nz, tau, slicing, lattice=lattice)
     o.init_fields(u0)
-    with _fp32(shape, tau, slicing) as g:
+    with _fp32(shape, tau, slicing, lattice) as g:
         g.init_fields(u0)
         done = 0
         for n in horizons:
@@ -144,7 +146,7 @@ def test_fp32_error_norms_and_kernel_names():
         g.init_fields(u0)
         g.set_timing(True)
         g.step(2)
-        assert set(g.kernel_times()) == {"lbnr::k_moments32", "lbnr::k_collide32"}  # 12 x 10: split path
+        assert set(g.kernel_times()) == {"lbnr::k_moments32<lbnr::D3Q19>", "lbnr::k_collide32<lbnr::D3Q19>"}
         u = g.moments()
         nr = g.error_norms(torch.from_numpy(ref).cuda())
     assert np.array_equal(nr["max_abs"], np.abs(u - ref).reshape(16, -1).max(axis=1))

@@ -10,7 +10,8 @@ step at tau = 0.6), so any difference in operation order would grow past
 1e-12 within a few dozen steps.
 
 Cases span several 256-thread blocks with a ragged tail, degenerate extents
-(1 and 2 sites along an axis), both slicings, and the full-size 256^3
+(1 and 2 sites along an axis), both slicings, both lattices (D3Q19, and D2Q9
+on lattices one site thick), the linear wave, and the full-size 256^3
 diagonal wave (compared plane by plane with the oracle's 256 x 256 x 1 run,
 which the plane symmetry of that wave makes exact).
 """
@@ -31,24 +32,24 @@ def _torch():
     return torch
 
 
-def _gpu_lattice(shape, tau, slicing, path=0):
+def _gpu_lattice(shape, tau, slicing, path=0, lattice=19):
     from paper_1505_02037_amd import lb
 
     nz, ny, nx = shape
-    return lb.Lattice(nx, ny, nz, tau, slicing=slicing, device=0, path=path)
+    return lb.Lattice(nx, ny, nz, tau, slicing=slicing, device=0, path=path, lattice=lattice)
 
 
 def _say(msg):
     print(msg, flush=True)
 
 
-def _both(u0, tau, slicing, horizons, path=0):
+def _both(u0, tau, slicing, horizons, path=0, lattice=19):
     """Yield (n, gpu moments, gpu distributions, oracle moments, oracle distributions)."""
     shape = u0.shape[1:]
     nz, ny, nx = shape
-    o = oracle.Oracle(nx, ny, nz, tau, slicing)
+    o = oracle.Oracle(nx, ny, nz, tau, slicing, lattice=lattice)
     o.init_fields(u0)
-    with _gpu_lattice(shape, tau, slicing, path) as g:
+    with _gpu_lattice(shape, tau, slicing, path, lattice) as g:
         g.init_fields(u0)
         done = 0
         for n in horizons:
@@ -118,6 +119,45 @@ def test_linear_wave_bitwise(path):
     for n, ug, fg, uo, fo in _both(u0, 4.5, oracle.GEODESIC, (1, 25, 100), PATHS[path]):
         _assert_equal(fg, fo, f"distributions at step {n}")
         _assert_equal(ug, uo, f"moments at step {n}")
+
+
+CASES_D2Q9 = [
+    # (name, shape (1, ny, nx), tau, slicing, seed): several blocks and a
+    # ragged tail, degenerate widths, both slicings
+    ("d2q9_random_37x29", (1, 29, 37), 0.7, oracle.HARMONIC, 41),
+    ("d2q9_random_geodesic_300x3", (1, 3, 300), 0.9, oracle.GEODESIC, 42),
+    ("d2q9_random_1x17", (1, 17, 1), 0.8, oracle.HARMONIC, 43),
+    ("d2q9_random_2x1", (1, 1, 2), 0.6, oracle.HARMONIC, 44),
+]
+
+
+@pytest.mark.parametrize("name,shape,tau,slicing,seed", CASES_D2Q9, ids=[c[0] for c in CASES_D2Q9])
+def test_d2q9_random_state_bitwise(name, shape, tau, slicing, seed):
+    _torch()
+    _say(f"[parity] {name}")
+    nz, ny, nx = shape
+    u0 = workloads.random_state(nx, ny, nz, seed=seed, amp=0.05)
+    for n, ug, fg, uo, fo in _both(u0, tau, slicing, (0, 1, 2, 10, 30), lattice=oracle.D2Q9):
+        assert fg.shape == (16, 9) + shape
+        _assert_equal(fg, fo, f"{name} distributions at step {n}")
+        _assert_equal(ug, uo, f"{name} moments at step {n}")
+
+
+def test_d2q9_gauge_waves_bitwise():
+    """The paper's gauge-wave lattice: the x-wave (100 x 1, A = 0.01, tau =
+    0.6, 1000 steps, through the blow-up) and the (1,1,0) wave on 64 x 64
+    (tau = 1.0, 200 steps) equal the oracle's D2Q9 runs."""
+    _torch()
+    _say("[parity] d2q9 x-wave 100x1 tau=0.6 1000 steps")
+    u0 = workloads.gauge_wave_x(100, 1, 1, 0.01, 100.0)
+    for n, ug, fg, uo, fo in _both(u0, 0.6, oracle.HARMONIC, range(0, 1001, 200), lattice=oracle.D2Q9):
+        _assert_equal(fg, fo, f"x-wave distributions at step {n}")
+        _assert_equal(ug, uo, f"x-wave moments at step {n}")
+    _say("[parity] d2q9 diagonal wave 64x64 tau=1.0 200 steps")
+    u0 = workloads.gauge_wave_diag(64, 1, 0.1)
+    for n, ug, fg, uo, fo in _both(u0, 1.0, oracle.HARMONIC, (1, 50, 200), lattice=oracle.D2Q9):
+        _assert_equal(fg, fo, f"diagonal distributions at step {n}")
+        _assert_equal(ug, uo, f"diagonal moments at step {n}")
 
 
 def test_gauge_wave_3d_x_128_resolution_pieces():
@@ -213,9 +253,14 @@ def test_kernel_timing_names_the_launched_kernels():
     _torch()
     from paper_1505_02037_amd import lb
 
-    for path, names in ((1, {"lbnr::k_moments", "lbnr::k_collide"}), (2, {"lbnr::k_fused<double>"})):
-        with lb.Lattice(32, 32, 32, 0.6, device=0, path=path) as g:
-            g.init_fields(workloads.gauge_wave_x(32, 32, 32, 0.1, 32))
+    cases = (
+        (19, 32, 1, {"lbnr::k_moments<lbnr::D3Q19>", "lbnr::k_collide<lbnr::D3Q19>"}),
+        (19, 32, 2, {"lbnr::k_fused<double>"}),
+        (9, 1, 1, {"lbnr::k_moments<lbnr::D2Q9>", "lbnr::k_collide<lbnr::D2Q9>"}),
+    )
+    for lattice, nz, path, names in cases:
+        with lb.Lattice(32, 32, nz, 0.6, device=0, path=path, lattice=lattice) as g:
+            g.init_fields(workloads.gauge_wave_x(32, 32, nz, 0.1, 32))
             g.set_timing(True)
             g.step(3)
             t = g.kernel_times()

@@ -98,3 +98,68 @@ def test_solutions_are_not_trivial():
         seen["offdiag"] = max(seen["offdiag"], min(abs(K[1]), abs(st[2]), abs(D[1])))
     for k, v in seen.items():
         assert v > 1e-2, (k, v)
+
+
+# --------------------------------------------------------------------------
+# matter: the energy-momentum terms of S_ij and Omega_k
+# --------------------------------------------------------------------------
+
+MATTER_CASES = [
+    ("flrw_stiff", 0), ("flrw_stiff", 1), ("flrw_dust", 1),
+    ("flrw_stiff_sheared", 0), ("flrw_dust_sheared", 0),
+    ("manufactured", 0), ("manufactured", 1),
+]
+
+
+def test_einstein_tensor_helper_gives_the_friedmann_fluid():
+    """The helper that turns a metric into its energy-momentum tensor is
+    itself pinned by the Friedmann equations: for a = t^(1/3) (the paper's
+    stiff fluid) G^00 = rho = P = 1/(3 t^2) and G_ij = P gamma_ij; for dust,
+    a = t^(2/3), rho = 4/(3 t^2) and P = 0; vacuum solutions give zero."""
+    for tt in (1.0, 1.7):
+        G = es.einstein_matter("flrw_stiff", (tt, 0.1, 0.2, 0.3))
+        rho = 1.0 / (3.0 * tt * tt)
+        g = tt ** (2.0 / 3.0)
+        assert np.allclose(G, [rho, 0, 0, 0, rho * g, 0, 0, rho * g, 0, rho * g], rtol=1e-14, atol=1e-15)
+        G = es.einstein_matter("flrw_dust", (tt, 0.1, 0.2, 0.3))
+        assert np.allclose(G, [4.0 / (3.0 * tt * tt)] + [0.0] * 9, rtol=1e-14, atol=1e-15)
+    for name in ("schwarzschild_isotropic_sheared", "kasner_sheared"):
+        sol, _, _ = es.compiled(name)
+        assert np.abs(es.einstein_matter(name, sol.points[0])).max() < 1e-14
+
+
+@pytest.mark.parametrize("name,ip", MATTER_CASES)
+def test_matter_solution_satisfies_oracle_equations(name, ip):
+    """Every metric solves the Einstein equations with the energy-momentum
+    tensor taken as its Einstein tensor; with that matter the oracle's
+    sources must satisfy the evolution equations point-wise.  The FLRW cases
+    carry the paper's fluid (isotropic pressure, energy density); the
+    manufactured spacetime has momentum density G^0_k and anisotropic
+    stresses, with a varying lapse."""
+    sol, _, _ = es.compiled(name)
+    P = sol.points[ip]
+    st, dt = es.evaluate(name, P)
+    G = es.einstein_matter(name, P)
+    slicing = oracle.GEODESIC
+    r = oracle.point_rhs(st[0], st[1:7], st[7:13], st[13:16], st[16:19], st[19:37], slicing, matter=G)
+    vac = _rhs(st, slicing)
+    scale = 1.0 + max(np.abs(dt).max(), np.abs(r["R_K"]).max(), np.abs(r["Omega"]).max())
+    tol = 1e-10 * scale
+    assert np.abs(dt[1:7] - r["R_gamma"]).max() <= tol
+    if sol.slicing is not None:
+        assert abs(dt[0] - r["R_alpha"]) <= tol
+    assert np.abs(dt[13:16] - r["Omega"]).max() <= tol
+    div = _flux_divergence(name, P, slicing)
+    assert np.abs(dt[7:13] + div - r["R_K"]).max() <= 1e-9 * scale
+    # the matter terms are not vacuous for these cases.  For dust the energy
+    # density's two terms in S_ij (from -R4_ij and from the bracket) cancel,
+    # so the dust cases pin that cancellation rather than a net source.
+    if not name.startswith("flrw_dust"):
+        assert np.abs(dt[7:13] + div - vac["R_K"]).max() > 1e-3 or np.abs(dt[13:16] - vac["Omega"]).max() > 1e-3
+
+
+def test_manufactured_matter_is_general():
+    """Guard against vacuity: the manufactured spacetime's matter has energy
+    density, momentum density and off-diagonal stress."""
+    G = es.einstein_matter("manufactured", es.SOLUTIONS["manufactured"]().points[0])
+    assert abs(G[0]) > 1e-2 and np.abs(G[1:4]).min() > 1e-3 and np.abs(G[[5, 6, 8]]).max() > 1e-2

@@ -359,3 +359,83 @@ def test_d2q9_paper_gauge_wave():
         d = np.abs(u9 - o19.moments()).max(axis=(1, 2, 3))
         assert d.max() <= 2e-15 * math.exp(3.2e-3 * n)
     assert life is not None and 1500 <= life <= 3000, life
+
+
+def _flrw_run(dt, T=1.0, tau=3.0, w=1.0, shape=(4, 4, 4), every=100):
+    """The paper's FLRW setup: a homogeneous lattice, geodesic slicing, the
+    fluid (rho, P) of the exact solution set before each step and before each
+    read-out.  Returns [(t, gamma_xx rel. error, K_xx rel. error, moments)]."""
+    nz, ny, nx = shape
+    o = oracle.Oracle(nx, ny, nz, tau, oracle.GEODESIC)
+    o.set_matter(workloads.flrw_fluid(1.0, dt, w), oracle.MATTER_FLUID)
+    o.init_fields(workloads.flrw_fields(nx, ny, nz, dt, 1.0, w))
+    out = []
+    n_end = int(round(T / dt))
+    for n in range(n_end + 1):
+        t = 1.0 + n * dt
+        o.set_matter(workloads.flrw_fluid(t, dt, w), oracle.MATTER_FLUID)
+        if n % every == 0 or n == n_end:
+            u = o.moments()
+            g, k, _, _ = workloads.flrw_exact(t, w)
+            out.append((t, u[1].max() / g - 1.0, u[7].max() / (k * dt) - 1.0, u))
+        if n < n_end:
+            o.step(1)
+    return out
+
+
+def test_flrw_paper_setup():
+    """Section "Expansion of flat universe": 4^3 lattice, dt = 0.001,
+    tau/dt = 3, P = rho = 1/(3 t^2), gamma from 1 at t = 1.  The lattice stays
+    homogeneous (every site identical), the metric follows t^(2/3) and K
+    follows -t^(-1/3)/3.  The relative error of K rises and levels off near
+    2e-5 (the value the paper's error figure for this test levels off at);
+    that of the metric stays below 6e-5."""
+    res = _flrw_run(1e-3)
+    for t, eg, ek, u in res:
+        assert np.all(u == u[:, :1, :1, :1]), t
+        assert abs(eg) <= 6e-5 and abs(ek) <= 3e-5, (t, eg, ek)
+        # the lapse stays 1 to the rounding of the weights (sum 1 + 2^-52)
+        assert np.abs(u[0] - 1.0).max() <= 1e-12
+        assert np.all(u[[2, 3, 5, 8, 9, 11, 13, 14, 15]] == 0.0)
+    late = [abs(ek) for t, _, ek, _ in res if t >= 1.6]
+    assert 1.5e-5 <= min(late) and max(late) <= 2.5e-5, late
+
+
+def test_flrw_first_order_in_dt_and_independent_of_tau():
+    """The explicit half-source predictor makes the homogeneous evolution
+    first order in dt: halving dt halves the error at t = 2 (stiff fluid and
+    dust).  On a homogeneous lattice streaming moves nothing and the sum of
+    the relaxed distributions is ubar + R for every tau, so the moments do not
+    depend on tau."""
+    for w in (1.0, 0.0):
+        e1 = _flrw_run(2e-3, w=w, shape=(1, 1, 1))[-1]
+        e2 = _flrw_run(1e-3, w=w, shape=(1, 1, 1))[-1]
+        for a, b in ((e1[1], e2[1]), (e1[2], e2[2])):
+            assert 1.9 <= a / b <= 2.1, (w, a, b)
+    ua = _flrw_run(1e-3, T=0.2, tau=3.0, shape=(1, 1, 1))[-1][3]
+    ub = _flrw_run(1e-3, T=0.2, tau=0.7, shape=(1, 1, 1))[-1][3]
+    assert np.allclose(ua, ub, rtol=1e-13, atol=1e-20)
+
+
+def test_matter_fluid_equals_its_tensor():
+    """The fluid kind (rho, P) is the tensor G^00 = rho / alpha^2, G^0_k = 0,
+    G_ij = P gamma_ij at the site's lapse and metric.  The initialisation
+    evaluates the sources at u0, so a per-site tensor built from u0 must give
+    the initial distributions of the fluid kind to rounding, on a random
+    state with alpha != 1; and the matter must change them."""
+    u0 = workloads.random_state(5, 4, 3, seed=8, amp=0.03)
+    rho, P = 2e-3, 7e-4
+    G = np.zeros((10,) + u0.shape[1:])
+    G[0] = rho / u0[0] ** 2
+    for p in range(6):
+        G[4 + p] = P * u0[1 + p]
+    fl = oracle.Oracle(5, 4, 3, 0.9, oracle.GEODESIC)
+    fl.set_matter(np.array([rho, P]), oracle.MATTER_FLUID)
+    fl.init_fields(u0)
+    te = oracle.Oracle(5, 4, 3, 0.9, oracle.GEODESIC)
+    te.set_matter(G)
+    te.init_fields(u0)
+    va = oracle.Oracle(5, 4, 3, 0.9, oracle.GEODESIC)
+    va.init_fields(u0)
+    assert np.abs(fl.distributions() - te.distributions()).max() <= 1e-18
+    assert np.abs(fl.distributions() - va.distributions()).max() >= 1e-5

@@ -1,7 +1,8 @@
 """Seeded synthetic inputs shared by the GPU path's callers and the oracle's tests.
 
-This package holds closed-form initial data (the gauge and linear waves of the
-paper's validation section), seeded noise and seeded request traces.  It holds
+This package holds closed-form initial data (the gauge and linear waves and
+the FLRW universe of the paper's validation section, with the FLRW fluid's
+density and pressure), seeded noise and seeded request traces.  It holds
 none of the lattice Boltzmann arithmetic: no equilibria, no sources, no
 streaming.  Every array it returns is float64 with the field-major layout
 ``u[field, z, y, x]`` (x fastest) that both the oracle and the C-ABI take.
@@ -27,4 +28,5 @@ from .gauge import (  # noqa: F401
     crossing_steps_x,
     crossing_steps_diag,
 )
+from .flrw import flrw_exact, flrw_fields, flrw_fluid  # noqa: F401
 from .trace import request_trace  # noqa: F401
