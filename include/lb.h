@@ -110,6 +110,28 @@ int lb_moments(lb_handle *h, double *u_out, int on_device);
  * Synchronises the handle's stream. */
 int lb_get_distributions(lb_handle *h, double *f_out, int on_device);
 
+/* Matter: the energy-momentum tensor G (units c = 8 pi G = 1, lattice units)
+ * in the sources of the extrinsic-curvature and momentum-variable equations
+ * (section "Bona-Masso evolution equations"; section "Expansion of flat
+ * universe" for the fluid).  Two kinds:
+ *   LB_MATTER_TENSOR  10 values: G^00, G^0_k (x, y, z), G_ij (xx, xy, xz, yy,
+ *                     yz, zz);
+ *   LB_MATTER_FLUID    2 values: rho and P of a perfect fluid at rest in the
+ *                     slicing; alpha^2 G^00 = rho, G^0_k = 0, G_ij = P gamma_ij
+ *                     at each site's lapse and metric.
+ * per_site = 0: M holds the values for every site; 1: M is [ncomp][nz][ny][nx].
+ * M = NULL returns to vacuum.  The matter set enters every later call that
+ * evaluates the sources (lb_init_fields, lb_step, lb_moments, lb_error_norms)
+ * until it is changed; values for every site are carried in the launch
+ * arguments, values per site are copied to the device (stream-ordered after
+ * the steps already enqueued).  A time-dependent matter field is followed by
+ * setting it before each step (the step from time n uses the matter of time
+ * n) and before each read-out.  LB_EINVAL on an unknown kind, or on a handle
+ * of the fused path (its launch evaluates vacuum sources only). */
+#define LB_MATTER_TENSOR 0
+#define LB_MATTER_FLUID 1
+int lb_set_matter(lb_handle *h, int kind, const double *M, int per_site, int on_device);
+
 /* Error norms of the current fields against u_ref ([16][nz][ny][nx]),
  * computed on the device in FP64.  Per field F (arrays of 16):
  *   max_abs[F] = max_x |u_F - ref_F|,  l2[F] = sqrt(sum_x (u_F - ref_F)^2 / N),

@@ -55,12 +55,14 @@ struct lb_handle {
     int device = -1;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    void *fbuf[2] = {nullptr, nullptr};   // distribution buffers [16][19][ps] (double or float)
+    void *fbuf[2] = {nullptr, nullptr};   // distribution buffers [16][Q][ps] (double or float)
     double *ubar = nullptr;               // [16][ps] moments of the current state
     double *ubar2 = nullptr;              // [16][ps] next step's moments (fused path)
     bool ubar_valid = false;              // ubar holds the current state's moments
     bool fused = false;                   // one launch per step
     double *lm = nullptr;                 // [7][ps]
+    lbnr::MatterArg matter;               // matter in the sources (kind < 0: vacuum)
+    double *matter_buf = nullptr;         // [10][ps] per-site matter values, allocated on first use
     int cur = 0;                          // buffer holding the current state
     bool initialised = false;
     long long steps = 0;
@@ -126,9 +128,9 @@ hipError_t run_collide(lb_handle *h)
     const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
     if (fp32(h))
         return lbnr::launch_collide32((const float *)h->fbuf[h->cur], (float *)h->fbuf[h->cur ^ 1], h->G, harmonic,
-                                      h->omega, h->srcfac, h->ubar, h->lm, h->stream);
+                                      h->omega, h->srcfac, h->ubar, h->lm, h->matter, h->stream);
     return lbnr::launch_collide((const double *)h->fbuf[h->cur], (double *)h->fbuf[h->cur ^ 1], h->G, harmonic,
-                                h->omega, h->srcfac, h->ubar, h->lm, h->stream);
+                                h->omega, h->srcfac, h->ubar, h->lm, h->matter, h->stream);
 }
 
 void free_all(lb_handle *h)
@@ -138,6 +140,7 @@ void free_all(lb_handle *h)
     if (h->ubar) (void)hipFree(h->ubar);
     if (h->ubar2) (void)hipFree(h->ubar2);
     if (h->lm) (void)hipFree(h->lm);
+    if (h->matter_buf) (void)hipFree(h->matter_buf);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
@@ -237,9 +240,9 @@ int lb_init_fields(lb_handle *h, const double *u0, int on_device)
     }
     const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
     if (fp32(h))
-        LB_HIP(lbnr::launch_init32(G, harmonic, du0, h->lm, (float *)h->fbuf[h->cur], h->stream));
+        LB_HIP(lbnr::launch_init32(G, harmonic, du0, h->lm, (float *)h->fbuf[h->cur], h->matter, h->stream));
     else
-        LB_HIP(lbnr::launch_init(G, harmonic, du0, h->lm, (double *)h->fbuf[h->cur], h->stream));
+        LB_HIP(lbnr::launch_init(G, harmonic, du0, h->lm, (double *)h->fbuf[h->cur], h->matter, h->stream));
     // the caller may release u0 as soon as this returns
     LB_HIP(hipStreamSynchronize(h->stream));
     h->initialised = true;
@@ -319,7 +322,7 @@ int lb_moments(lb_handle *h, double *u_out, int on_device)
     const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
     double *dst = on_device ? u_out : spare(h);
     LB_HIP(run_moments(h));
-    LB_HIP(lbnr::launch_output(G, harmonic, h->ubar, h->lm, dst, h->stream));
+    LB_HIP(lbnr::launch_output(G, harmonic, h->ubar, h->lm, dst, h->matter, h->stream));
     if (!on_device)
         LB_HIP(hipMemcpyAsync(u_out, dst, (size_t)16 * G.nsite * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     LB_HIP(hipStreamSynchronize(h->stream));
@@ -367,7 +370,7 @@ int lb_error_norms(lb_handle *h, const double *u_ref, int on_device, double *max
     double *ref = u + (size_t)16 * G.nsite;
     double *scratch = ref + (size_t)16 * G.nsite;
     LB_HIP(run_moments(h));
-    LB_HIP(lbnr::launch_output(G, harmonic, h->ubar, h->lm, u, h->stream));
+    LB_HIP(lbnr::launch_output(G, harmonic, h->ubar, h->lm, u, h->matter, h->stream));
     const double *dref = u_ref;
     if (!on_device) {
         LB_HIP(hipMemcpyAsync(ref, u_ref, (size_t)16 * G.nsite * sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -383,6 +386,52 @@ int lb_error_norms(lb_handle *h, const double *u_ref, int on_device, double *max
         if (l2) l2[F] = res[F * 3 + 1];
         if (ref_max) ref_max[F] = res[F * 3 + 2];
     }
+    return LB_OK;
+}
+
+int lb_set_matter(lb_handle *h, int kind, const double *M, int per_site, int on_device)
+{
+    if (!h) return LB_EINVAL;
+    if (kind != LB_MATTER_TENSOR && kind != LB_MATTER_FLUID) return LB_EINVAL;
+    if (!M) {
+        h->matter.kind = -1;
+        h->matter.field = nullptr;
+        return LB_OK;
+    }
+    if (h->fused) return LB_EINVAL; // the z-marching launch evaluates vacuum sources only
+    DeviceGuard dg(h->device);
+    const int nc = kind == LB_MATTER_FLUID ? 2 : 10;
+    const Geom &G = h->G;
+    if (!per_site) {
+        double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (on_device) {
+            LB_HIP(hipMemcpyAsync(v, M, nc * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            LB_HIP(hipStreamSynchronize(h->stream));
+        } else {
+            for (int c = 0; c < nc; ++c) v[c] = M[c];
+        }
+        // carried by value in the arguments of every later launch
+        for (int c = 0; c < 10; ++c) h->matter.uni[c] = v[c];
+        h->matter.field = nullptr;
+        h->matter.kind = kind;
+        return LB_OK;
+    }
+    if (!h->matter_buf) {
+        hipError_t e = hipMalloc((void **)&h->matter_buf, (size_t)10 * G.ps * sizeof(double));
+        if (e != hipSuccess) {
+            h->matter_buf = nullptr;
+            snprintf(g_last_error, sizeof g_last_error, "hipMalloc: %s", hipGetErrorString(e));
+            (void)hipGetLastError();
+            return e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE;
+        }
+    }
+    // [nc][nsite] into planes of ps; ordered after the launches already queued
+    LB_HIP(hipMemcpy2DAsync(h->matter_buf, G.ps * sizeof(double), M, (size_t)G.nsite * sizeof(double),
+                            (size_t)G.nsite * sizeof(double), nc,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+    if (!on_device) LB_HIP(hipStreamSynchronize(h->stream));
+    h->matter.field = h->matter_buf;
+    h->matter.kind = kind;
     return LB_OK;
 }
 

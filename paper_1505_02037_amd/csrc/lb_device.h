@@ -377,6 +377,43 @@ __device__ __forceinline__ void bm_flux(double alpha, const double g[6], const d
         }
 }
 
+// Matter (energy-momentum tensor G, units c = 8 pi G = 1) in the sources of
+// the extrinsic-curvature and momentum-variable equations (section
+// "Bona-Masso evolution equations"), of one of two kinds:
+//   kMatterTensor: M = G^00, G^0_k (x, y, z), G_ij (xx, xy, xz, yy, yz, zz);
+//   kMatterFluid:  M = (rho, P) of a perfect fluid at rest in the slicing:
+//                  alpha^2 G^00 = rho, G^0_k = 0, G_ij = P gamma_ij.
+// With R4_ij = G_ij - gamma_ij/2 (-alpha^2 G^00 + tr G), tr G = gamma^{ij} G_ij,
+// S_ij gains gamma_ij/4 (2 alpha^2 G^00) - R4_ij (added to the vacuum value
+// as one sum) and Omega_k gains alpha (alpha G^0_k).
+constexpr int kMatterTensor = 0;
+constexpr int kMatterFluid = 1;
+
+__device__ __forceinline__ void matter_sources(double alpha, const double g[6], const double gi[6], int kind,
+                                               const double M[10], double S[6], double Om[3])
+{
+    double Gm[6], a2G;
+    if (kind == kMatterFluid) {
+#pragma unroll
+        for (int p = 0; p < 6; ++p) Gm[p] = M[1] * g[p];
+        a2G = M[0];
+    } else {
+#pragma unroll
+        for (int p = 0; p < 6; ++p) Gm[p] = M[4 + p];
+        a2G = alpha * alpha * M[0];
+    }
+    const double trG = trace_up(gi, Gm);
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const double R4 = Gm[p] - 0.5 * g[p] * (-a2G + trG);
+        S[p] += 0.25 * g[p] * (2.0 * a2G) - R4;
+    }
+    if (kind == kMatterTensor) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Om[k] += alpha * (alpha * M[1 + k]);
+    }
+}
+
 // c_q . F for the three flux components of one K pair (only the non-zero
 // velocity components enter; each direction has at most two).
 template <int q, class L = D3Q19>

@@ -27,13 +27,14 @@ __global__ void __launch_bounds__(256) k_moments32(const float *__restrict__ fin
     if (s < G.nsite) moments_site32<L>(fin, G, s, harmonic, ubar, lm);
 }
 
-template <class L>
+template <class L, bool HasMatter>
 __global__ void __launch_bounds__(256) k_collide32(const float *__restrict__ fin, float *__restrict__ fout, Geom G,
                                                    int harmonic, double omega, double srcfac,
-                                                   const double *__restrict__ ubar, const double *__restrict__ lm)
+                                                   const double *__restrict__ ubar, const double *__restrict__ lm,
+                                                   MatterArg m)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) collide_site32<L>(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm);
+    if (s < G.nsite) collide_site32<L, HasMatter>(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm, m);
 }
 
 // initial deviations: d_q = f^eq_q(u0) - w_q R(u0)/2 - w_q u_rest (FP64, then rounded)
@@ -60,9 +61,9 @@ __device__ __forceinline__ void init32_field(float *__restrict__ fout, const Geo
     if constexpr (Fld + 1 < kFields) init32_field<Fld + 1>(fout, G, o, P);
 }
 
-template <class L>
+template <class L, bool HasMatter>
 __global__ void __launch_bounds__(256) k_init32(Geom G, int harmonic, const double *__restrict__ u0,
-                                                const double *__restrict__ lm, float *__restrict__ fout)
+                                                const double *__restrict__ lm, float *__restrict__ fout, MatterArg m)
 {
     SiteT<L> o;
     if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
@@ -76,6 +77,11 @@ __global__ void __launch_bounds__(256) k_init32(Geom G, int harmonic, const doub
     stencil(G, o, lm, u[0], A, D);
     sym_inverse(u + 1, gi);
     bm_sources(u[0], u + 1, gi, u + 7, u + 13, A, D, S, Om);
+    if constexpr (HasMatter) {
+        double M[10];
+        matter_load(m, G, o.s, M);
+        matter_sources(u[0], u + 1, gi, m.kind, M, S, Om);
+    }
 #pragma unroll
     for (int F = 0; F < kFields; ++F) P.u[F] = u[F];
 #pragma unroll
@@ -114,25 +120,40 @@ hipError_t launch_moments32(const float *fin, const Geom &G, int harmonic, doubl
 }
 
 hipError_t launch_collide32(const float *fin, float *fout, const Geom &G, int harmonic, double omega, double srcfac,
-                            const double *ubar, const double *lm, hipStream_t st)
+                            const double *ubar, const double *lm, const MatterArg &m, hipStream_t st)
 {
-    if (G.nq == D2Q9::Q)
-        hipLaunchKernelGGL(k_collide32<D2Q9>, grid32(G.nsite), dim3(256), 0, st, fin, fout, G, harmonic, omega,
-                           srcfac, ubar, lm);
+    const dim3 grid = grid32(G.nsite), blk(256);
+    const bool q9 = G.nq == D2Q9::Q, mat = m.kind >= 0;
+    if (q9 && mat)
+        hipLaunchKernelGGL((k_collide32<D2Q9, true>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+                           lm, m);
+    else if (q9)
+        hipLaunchKernelGGL((k_collide32<D2Q9, false>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+                           lm, m);
+    else if (mat)
+        hipLaunchKernelGGL((k_collide32<D3Q19, true>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+                           lm, m);
     else
-        hipLaunchKernelGGL(k_collide32<D3Q19>, grid32(G.nsite), dim3(256), 0, st, fin, fout, G, harmonic, omega,
-                           srcfac, ubar, lm);
+        hipLaunchKernelGGL((k_collide32<D3Q19, false>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac,
+                           ubar, lm, m);
     return hipGetLastError();
 }
 
-hipError_t launch_init32(const Geom &G, int harmonic, const double *u0, double *lm, float *fout, hipStream_t st)
+hipError_t launch_init32(const Geom &G, int harmonic, const double *u0, double *lm, float *fout, const MatterArg &m,
+                         hipStream_t st)
 {
     hipError_t e = launch_copy_lm(G, u0, lm, st);
     if (e != hipSuccess) return e;
-    if (G.nq == D2Q9::Q)
-        hipLaunchKernelGGL(k_init32<D2Q9>, grid32(G.nsite), dim3(256), 0, st, G, harmonic, u0, lm, fout);
+    const dim3 grid = grid32(G.nsite), blk(256);
+    const bool q9 = G.nq == D2Q9::Q, mat = m.kind >= 0;
+    if (q9 && mat)
+        hipLaunchKernelGGL((k_init32<D2Q9, true>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+    else if (q9)
+        hipLaunchKernelGGL((k_init32<D2Q9, false>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+    else if (mat)
+        hipLaunchKernelGGL((k_init32<D3Q19, true>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
     else
-        hipLaunchKernelGGL(k_init32<D3Q19>, grid32(G.nsite), dim3(256), 0, st, G, harmonic, u0, lm, fout);
+        hipLaunchKernelGGL((k_init32<D3Q19, false>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
     return hipGetLastError();
 }
 

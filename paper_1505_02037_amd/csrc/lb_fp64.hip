@@ -39,20 +39,22 @@ __global__ void __launch_bounds__(256) k_moments(const double *__restrict__ fin,
 // ---------------------------------------------------------------------------
 // k_collide: sources, flux, BGK relaxation with source, pull streaming
 // ---------------------------------------------------------------------------
-template <class L>
+template <class L, bool HasMatter>
 __global__ void __launch_bounds__(256) k_collide(const double *__restrict__ fin, double *__restrict__ fout,
                                                  Geom G, int harmonic, double omega, double srcfac,
-                                                 const double *__restrict__ ubar, const double *__restrict__ lm)
+                                                 const double *__restrict__ ubar, const double *__restrict__ lm,
+                                                 MatterArg m)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) collide_site64<L>(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm);
+    if (s < G.nsite) collide_site64<L, HasMatter>(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm, m);
 }
 
 // ---------------------------------------------------------------------------
 // k_output: the half-source moments u = ubar + R/2 into an unpadded array
 // ---------------------------------------------------------------------------
+template <bool HasMatter>
 __global__ void __launch_bounds__(256) k_output(Geom G, int harmonic, const double *__restrict__ ubar,
-                                                const double *__restrict__ lm, double *__restrict__ u)
+                                                const double *__restrict__ lm, double *__restrict__ u, MatterArg m)
 {
     Site o;
     if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
@@ -60,7 +62,7 @@ __global__ void __launch_bounds__(256) k_output(Geom G, int harmonic, const doub
 #pragma unroll
     for (int F = 0; F < kFields; ++F) ub[F] = ubar[(size_t)F * G.ps + o.s];
     Params P;
-    site_params(G, o, harmonic, ub, lm, P);
+    site_params<HasMatter>(G, o, harmonic, ub, lm, P, m);
 #pragma unroll
     for (int F = 0; F < kFields; ++F) u[(size_t)F * G.nsite + o.s] = P.u[F];
 }
@@ -95,9 +97,9 @@ __device__ __forceinline__ void init_field(double *__restrict__ fout, const Geom
     if constexpr (Fld + 1 < kFields) init_field<Fld + 1>(fout, G, o, P);
 }
 
-template <class L>
+template <class L, bool HasMatter>
 __global__ void __launch_bounds__(256) k_init(Geom G, int harmonic, const double *__restrict__ u0,
-                                              const double *__restrict__ lm, double *__restrict__ fout)
+                                              const double *__restrict__ lm, double *__restrict__ fout, MatterArg m)
 {
     SiteT<L> o;
     if (!site_of(G, blockIdx.x * blockDim.x + threadIdx.x, o)) return;
@@ -112,6 +114,11 @@ __global__ void __launch_bounds__(256) k_init(Geom G, int harmonic, const double
     stencil(G, o, lm, u[0], A, D);
     sym_inverse(u + 1, gi);
     bm_sources(u[0], u + 1, gi, u + 7, u + 13, A, D, S, Om);
+    if constexpr (HasMatter) {
+        double M[10];
+        matter_load(m, G, o.s, M);
+        matter_sources(u[0], u + 1, gi, m.kind, M, S, Om);
+    }
 #pragma unroll
     for (int F = 0; F < kFields; ++F) P.u[F] = u[F];
 #pragma unroll
@@ -216,20 +223,32 @@ hipError_t launch_moments(const double *fin, const Geom &G, int harmonic, double
 }
 
 hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int harmonic, double omega,
-                          double srcfac, const double *ubar, const double *lm, hipStream_t st)
+                          double srcfac, const double *ubar, const double *lm, const MatterArg &m, hipStream_t st)
 {
-    if (G.nq == D2Q9::Q)
-        hipLaunchKernelGGL(k_collide<D2Q9>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, fout, G, harmonic, omega,
-                           srcfac, ubar, lm);
+    const dim3 grid = grid_for(G.nsite, 256), blk(256);
+    const bool q9 = G.nq == D2Q9::Q, mat = m.kind >= 0;
+    if (q9 && mat)
+        hipLaunchKernelGGL((k_collide<D2Q9, true>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+                           lm, m);
+    else if (q9)
+        hipLaunchKernelGGL((k_collide<D2Q9, false>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+                           lm, m);
+    else if (mat)
+        hipLaunchKernelGGL((k_collide<D3Q19, true>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+                           lm, m);
     else
-        hipLaunchKernelGGL(k_collide<D3Q19>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, fout, G, harmonic, omega,
-                           srcfac, ubar, lm);
+        hipLaunchKernelGGL((k_collide<D3Q19, false>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+                           lm, m);
     return hipGetLastError();
 }
 
-hipError_t launch_output(const Geom &G, int harmonic, const double *ubar, const double *lm, double *u, hipStream_t st)
+hipError_t launch_output(const Geom &G, int harmonic, const double *ubar, const double *lm, double *u,
+                         const MatterArg &m, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_output, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, ubar, lm, u);
+    if (m.kind >= 0)
+        hipLaunchKernelGGL(k_output<true>, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, ubar, lm, u, m);
+    else
+        hipLaunchKernelGGL(k_output<false>, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, ubar, lm, u, m);
     return hipGetLastError();
 }
 
@@ -239,14 +258,21 @@ hipError_t launch_copy_lm(const Geom &G, const double *u0, double *lm, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm, double *fout, hipStream_t st)
+hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm, double *fout, const MatterArg &m,
+                       hipStream_t st)
 {
     hipError_t e = launch_copy_lm(G, u0, lm, st);
     if (e != hipSuccess) return e;
-    if (G.nq == D2Q9::Q)
-        hipLaunchKernelGGL(k_init<D2Q9>, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, u0, lm, fout);
+    const dim3 grid = grid_for(G.nsite, 256), blk(256);
+    const bool q9 = G.nq == D2Q9::Q, mat = m.kind >= 0;
+    if (q9 && mat)
+        hipLaunchKernelGGL((k_init<D2Q9, true>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+    else if (q9)
+        hipLaunchKernelGGL((k_init<D2Q9, false>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+    else if (mat)
+        hipLaunchKernelGGL((k_init<D3Q19, true>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
     else
-        hipLaunchKernelGGL(k_init<D3Q19>, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, u0, lm, fout);
+        hipLaunchKernelGGL((k_init<D3Q19, false>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
     return hipGetLastError();
 }
 

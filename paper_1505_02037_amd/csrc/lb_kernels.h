@@ -15,13 +15,25 @@ struct Geom {
     int nq = 19;     // directions of the lattice: 19 (D3Q19) or 9 (D2Q9, nz = 1)
 };
 
+// Matter in the sources, as the kernels take it: the values of one kind
+// (10 for the tensor kind, 2 for the fluid kind) either per site, from
+// `field` ([ncomp][ps]), or the same at every site, from `uni` (carried in the
+// kernel arguments).  kind < 0: vacuum.
+struct MatterArg {
+    const double *field = nullptr;
+    int kind = -1;
+    double uni[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+};
+
 // FP64 form (lb_fp64.hip); the split-step launchers, the initialisation and
 // the gather run the lattice G.nq names
 hipError_t launch_moments(const double *fin, const Geom &G, int harmonic, double *ubar, double *lm, hipStream_t st);
 hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int harmonic, double omega,
-                          double srcfac, const double *ubar, const double *lm, hipStream_t st);
-hipError_t launch_output(const Geom &G, int harmonic, const double *ubar, const double *lm, double *u, hipStream_t st);
-hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm, double *fout, hipStream_t st);
+                          double srcfac, const double *ubar, const double *lm, const MatterArg &m, hipStream_t st);
+hipError_t launch_output(const Geom &G, int harmonic, const double *ubar, const double *lm, double *u,
+                         const MatterArg &m, hipStream_t st);
+hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm, double *fout, const MatterArg &m,
+                       hipStream_t st);
 hipError_t launch_gather(const double *fin, const Geom &G, double *f, hipStream_t st);
 hipError_t launch_copy_lm(const Geom &G, const double *u0, double *lm, hipStream_t st);
 size_t norm_scratch_doubles(const Geom &G);
@@ -30,8 +42,9 @@ hipError_t launch_norms(const Geom &G, const double *u, const double *ref, doubl
 // FP32-deviation form (lb_fp32.hip); the output and norm kernels are shared
 hipError_t launch_moments32(const float *fin, const Geom &G, int harmonic, double *ubar, double *lm, hipStream_t st);
 hipError_t launch_collide32(const float *fin, float *fout, const Geom &G, int harmonic, double omega, double srcfac,
-                            const double *ubar, const double *lm, hipStream_t st);
-hipError_t launch_init32(const Geom &G, int harmonic, const double *u0, double *lm, float *fout, hipStream_t st);
+                            const double *ubar, const double *lm, const MatterArg &m, hipStream_t st);
+hipError_t launch_init32(const Geom &G, int harmonic, const double *u0, double *lm, float *fout, const MatterArg &m,
+                         hipStream_t st);
 hipError_t launch_gather32(const float *fin, const Geom &G, int field, double *f, hipStream_t st);
 
 // one-launch z-marching step (lb_fused.hip): reads this step's moments

@@ -340,9 +340,9 @@ int admit(lb_server *s)
         double *stage = (double *)d.f[1];
         SV_HIP(hipMemcpyAsync(stage, r.u0.data(), r.u0.size() * sizeof(double), hipMemcpyHostToDevice, s->stream));
         if (f32)
-            SV_HIP(lbnr::launch_init32(r.G, d.harmonic, stage, d.lm, (float *)d.f[0], s->stream));
+            SV_HIP(lbnr::launch_init32(r.G, d.harmonic, stage, d.lm, (float *)d.f[0], lbnr::MatterArg{}, s->stream));
         else
-            SV_HIP(lbnr::launch_init(r.G, d.harmonic, stage, d.lm, (double *)d.f[0], s->stream));
+            SV_HIP(lbnr::launch_init(r.G, d.harmonic, stage, d.lm, (double *)d.f[0], lbnr::MatterArg{}, s->stream));
         SV_HIP(hipStreamSynchronize(s->stream));
         std::vector<double>().swap(r.u0);
         r.state = LB_REQ_RUNNING;
@@ -381,7 +381,7 @@ int harvest(lb_server *s)
             SV_HIP(lbnr::launch_moments32((const float *)d.f[d.cur], r.G, d.harmonic, d.ubar, d.lm, s->stream));
         else
             SV_HIP(lbnr::launch_moments((const double *)d.f[d.cur], r.G, d.harmonic, d.ubar, d.lm, s->stream));
-        SV_HIP(lbnr::launch_output(r.G, d.harmonic, d.ubar, d.lm, out, s->stream));
+        SV_HIP(lbnr::launch_output(r.G, d.harmonic, d.ubar, d.lm, out, lbnr::MatterArg{}, s->stream));
         r.result.resize((size_t)16 * r.G.nsite);
         SV_HIP(hipMemcpyAsync(r.result.data(), out, r.result.size() * sizeof(double), hipMemcpyDeviceToHost,
                               s->stream));

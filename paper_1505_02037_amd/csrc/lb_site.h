@@ -80,10 +80,21 @@ struct Params {
     double F[18];
 };
 
+// matter values at site s (the kind's components; the rest zero)
+__device__ __forceinline__ void matter_load(const MatterArg &m, const Geom &G, uint32_t s, double M[10])
+{
+    const int nc = m.kind == kMatterFluid ? 2 : 10;
+#pragma unroll
+    for (int c = 0; c < 10; ++c) M[c] = c < nc ? (m.field ? m.field[(size_t)c * G.ps + s] : m.uni[c]) : 0.0;
+}
+
 // Collision parameters from the raw moments ub, the corrected lapse/metric c
-// with its right-hand sides Rag (lapse_metric(ub)), and the stencil A, D.
+// with its right-hand sides Rag (lapse_metric(ub)), and the stencil A, D;
+// with HasMatter, the matter M of kind mkind enters the sources.
+template <bool HasMatter = false>
 __device__ __forceinline__ void params_from(const double ub[kFields], const double c[7], const double Rag[7],
-                                            const double A[3], const double D[18], Params &P)
+                                            const double A[3], const double D[18], Params &P, int mkind = -1,
+                                            const double *M = nullptr)
 {
 #pragma unroll
     for (int F = 0; F < 7; ++F) {
@@ -94,6 +105,7 @@ __device__ __forceinline__ void params_from(const double ub[kFields], const doub
     double gi[6], S[6], Om[3], V[3];
     sym_inverse(c + 1, gi);
     bm_sources(alpha, c + 1, gi, ub + 7, ub + 13, A, D, S, Om);
+    if constexpr (HasMatter) matter_sources(alpha, c + 1, gi, mkind, M, S, Om);
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
         const double RK = alpha * S[p];
@@ -109,15 +121,21 @@ __device__ __forceinline__ void params_from(const double ub[kFields], const doub
     bm_flux(alpha, c + 1, gi, V, A, D, P.F);
 }
 
-template <class L>
+template <bool HasMatter = false, class L>
 __device__ __forceinline__ void site_params(const Geom &G, const SiteT<L> &o, int harmonic,
                                             const double ub[kFields], const double *__restrict__ lm,
-                                            Params &P)
+                                            Params &P, const MatterArg &m = MatterArg{})
 {
     double c[7], Rag[7], A[3], D[18];
     lapse_metric(ub, harmonic != 0, c, Rag);
     stencil(G, o, lm, c[0], A, D);
-    params_from(ub, c, Rag, A, D, P);
+    if constexpr (HasMatter) {
+        double M[10];
+        matter_load(m, G, o.s, M);
+        params_from<true>(ub, c, Rag, A, D, P, m.kind, M);
+    } else {
+        params_from(ub, c, Rag, A, D, P);
+    }
 }
 
 } // namespace lbnr

@@ -118,11 +118,11 @@ __device__ __forceinline__ void collide_all(const double *__restrict__ fin, doub
 }
 
 // sources, flux, BGK relaxation with source and pull streaming at site s
-template <class L = D3Q19>
+template <class L = D3Q19, bool HasMatter = false>
 __device__ __forceinline__ void collide_site64(const double *__restrict__ fin, double *__restrict__ fout,
                                                const Geom &G, uint32_t s, int harmonic, double omega,
                                                double srcfac, const double *__restrict__ ubar,
-                                               const double *__restrict__ lm)
+                                               const double *__restrict__ lm, const MatterArg &m = MatterArg{})
 {
     SiteT<L> o;
     site_of(G, s, o);
@@ -130,7 +130,7 @@ __device__ __forceinline__ void collide_site64(const double *__restrict__ fin, d
 #pragma unroll
     for (int F = 0; F < kFields; ++F) ub[F] = ubar[(size_t)F * G.ps + o.s];
     Params P;
-    site_params(G, o, harmonic, ub, lm, P);
+    site_params<HasMatter>(G, o, harmonic, ub, lm, P, m);
     pull_sources(G, o);
     collide_all<0>(fin, fout, G, o, P, omega, srcfac);
 }
@@ -216,11 +216,11 @@ __device__ __forceinline__ void collide32_all(const float *__restrict__ fin, flo
     if constexpr (Fld + 1 < kFields) collide32_all<Fld + 1>(fin, fout, G, o, P, om, srcfac);
 }
 
-template <class L = D3Q19>
+template <class L = D3Q19, bool HasMatter = false>
 __device__ __forceinline__ void collide_site32(const float *__restrict__ fin, float *__restrict__ fout,
                                                const Geom &G, uint32_t s, int harmonic, double omega,
                                                double srcfac, const double *__restrict__ ubar,
-                                               const double *__restrict__ lm)
+                                               const double *__restrict__ lm, const MatterArg &m = MatterArg{})
 {
     SiteT<L> o;
     site_of(G, s, o);
@@ -228,7 +228,7 @@ __device__ __forceinline__ void collide_site32(const float *__restrict__ fin, fl
 #pragma unroll
     for (int F = 0; F < kFields; ++F) ub[F] = ubar[(size_t)F * G.ps + o.s];
     Params P;
-    site_params(G, o, harmonic, ub, lm, P);
+    site_params<HasMatter>(G, o, harmonic, ub, lm, P, m);
     pull_sources(G, o);
     collide32_all<0>(fin, fout, G, o, P, (float)omega, srcfac);
 }

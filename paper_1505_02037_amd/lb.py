@@ -34,13 +34,15 @@ FP32_DEV = 1
 PATH_AUTO = 0
 PATH_SPLIT = 1
 PATH_FUSED = 2
+MATTER_TENSOR = 0
+MATTER_FLUID = 1
 NF = 16
 NQ = 19
 
 EXPORTS = (
     "lb_create", "lb_device_bytes", "lb_init_fields", "lb_step", "lb_moments",
     "lb_get_distributions", "lb_error_norms", "lb_steps_done", "lb_set_timing",
-    "lb_kernel_times", "lb_destroy", "lb_strerror", "lb_last_error",
+    "lb_kernel_times", "lb_set_matter", "lb_destroy", "lb_strerror", "lb_last_error",
 )
 
 
@@ -90,6 +92,7 @@ def load_library():
     lib.lb_set_timing.argtypes = [P, ctypes.c_int]
     lib.lb_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), dp, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int)]
+    lib.lb_set_matter.argtypes = [P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int]
     lib.lb_destroy.argtypes = [P]
     lib.lb_destroy.restype = None
     lib.lb_strerror.argtypes = [ctypes.c_int]
@@ -193,6 +196,21 @@ class Lattice:
         p, dev = _ptr(out, NF * self.nq * self.nsite)
         _check(self._lib.lb_get_distributions(self._h, p, dev), "lb_get_distributions")
         return out
+
+    def set_matter(self, M, kind: int = MATTER_TENSOR) -> None:
+        """Matter in lattice units (lb_set_matter): kind MATTER_TENSOR, M =
+        G^00, G^0_k, G_ij; kind MATTER_FLUID, M = (rho, P).  M with one value
+        per component applies at every site; (ncomp, nz, ny, nx) per site;
+        None returns to vacuum."""
+        if M is None:
+            _check(self._lib.lb_set_matter(self._h, int(kind), None, 0, 0), "lb_set_matter")
+            return
+        nc = 2 if kind == MATTER_FLUID else 10
+        if isinstance(M, (list, tuple)):
+            M = np.asarray(M, dtype=np.float64)
+        per_site = int(M.shape != (nc,))
+        p, dev = _ptr(M, nc * (self.nsite if per_site else 1))
+        _check(self._lib.lb_set_matter(self._h, int(kind), p, per_site, dev), "lb_set_matter")
 
     def error_norms(self, u_ref) -> dict:
         p, dev = _ptr(u_ref, NF * self.nsite)

@@ -110,6 +110,7 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.lb_moments(None, None, 0) == lb.LB_EINVAL
     assert lib.lb_init_fields(None, None, 0) == lb.LB_EINVAL
     assert lib.lb_steps_done(None) == -1
+    assert lib.lb_set_matter(None, 0, None, 0, 0) == lb.LB_EINVAL
     lib.lb_destroy(None)
     assert lib.lb_strerror(lb.LB_EINVAL) == b"invalid argument"
 

@@ -25,6 +25,7 @@ from .gauge import (  # noqa: F401
     minkowski,
     add_lapse_noise,
     random_state,
+    random_matter,
     crossing_steps_x,
     crossing_steps_diag,
 )

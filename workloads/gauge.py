@@ -142,6 +142,16 @@ def random_state(nx: int, ny: int, nz: int, seed: int, amp: float = 0.05) -> np.
     return u
 
 
+def random_matter(nx: int, ny: int, nz: int, seed: int, amp: float = 1e-3, ncomp: int = 10) -> np.ndarray:
+    """Seeded random matter values per site, shape (ncomp, nz, ny, nx):
+    U(-amp, amp) in every component (10 for a tensor G^00, G^0_k, G_ij;
+    2 for a fluid's rho, P, which are drawn in U(0, amp))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if ncomp == 2:
+        return amp * rng.uniform(0.0, 1.0, size=(2, nz, ny, nx))
+    return amp * rng.uniform(-1.0, 1.0, size=(ncomp, nz, ny, nx))
+
+
 def crossing_steps_x(d: float) -> float:
     """Steps for one crossing of a wave of wavelength d (light speed 1)."""
     return float(d)
