@@ -13,7 +13,8 @@ Prints one JSON line with the throughput in field-site updates per second
 8 B each way per site), and the CPU oracle timed on a bounded sample of the
 same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--form fp64|fp32]
+                    [--path split|fused] [--no-cpu]
 """
 
 from __future__ import annotations
@@ -35,7 +36,9 @@ FIELDS, Q = 16, 19
 ALG_BYTES_PER_SITE = {"fp64": 2 * FIELDS * Q * 8, "fp32": 2 * FIELDS * Q * 4}
 
 
-STEP_SOURCES = ("lb_api.hip", "lb_device.h", "lb_fp32.hip", "lb_fp64.hip", "lb_kernels.h", "lb_site.h", "lb_step.h")
+# the device sources the timed step kernels are compiled from (host-side
+# launch code is not part of a kernel)
+STEP_SOURCES = ("lb_device.h", "lb_fp32.hip", "lb_fp64.hip", "lb_kernels.h", "lb_site.h", "lb_step.h")
 
 
 def kernel_source_hash() -> str:
@@ -94,6 +97,8 @@ def main() -> int:
     ap.add_argument("--tau", type=float, default=0.6)
     ap.add_argument("--form", choices=("fp64", "fp32"), default="fp64",
                     help="fp64: plain FP64 step; fp32: FP32-deviation storage and relaxation")
+    ap.add_argument("--path", choices=("split", "fused"), default="split",
+                    help="split: two launches per step (the library's default); fused: one z-marching launch")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -114,7 +119,8 @@ def main() -> int:
     nsite = n * n * n
     stream = torch.cuda.Stream()
     precision = lb.FP64 if args.form == "fp64" else lb.FP32_DEV
-    g = lb.Lattice(n, n, n, tau, precision=precision, device=0, stream=stream.cuda_stream)
+    path = lb.PATH_SPLIT if args.path == "split" else lb.PATH_FUSED
+    g = lb.Lattice(n, n, n, tau, precision=precision, device=0, stream=stream.cuda_stream, path=path)
     with torch.cuda.stream(stream):
         u0 = torch.from_numpy(workloads.gauge_wave_diag(n, 1, 0.1)).cuda().expand(16, n, n, n).contiguous()
     stream.synchronize()
@@ -138,7 +144,7 @@ def main() -> int:
     step_kernel_ms = sum(ktimes.values())
     alg_bytes = ALG_BYTES_PER_SITE[args.form] * nsite
     achieved = alg_bytes / (step_kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(nsite, args.form)
+    traffic = measured_traffic(nsite, args.form) if args.path == "split" else None
     line = {
         "metric": "field-site updates/s",
         "value": value,
@@ -160,6 +166,7 @@ def main() -> int:
             "lattice": [n, n, n],
             "tau": tau,
             "form": args.form,
+            "path": args.path,
             "parallelism": "single GPU",
         },
         "roofline": {

@@ -72,6 +72,7 @@ struct lb_handle {
     std::vector<hipEvent_t> events;
     double ms_moments = 0.0, ms_collide = 0.0; // fused path: ms_moments holds the one kernel
     bool timed_fused = false;
+    bool timed_matter = false;
     long long timed_launches = 0;
 };
 
@@ -309,6 +310,7 @@ int lb_step(lb_handle *h, long long nsteps)
         h->ms_collide = tc / (double)nsteps;
         h->timed_launches = nsteps;
         h->timed_fused = h->fused;
+        h->timed_matter = h->matter.kind >= 0;
     }
     return LB_OK;
 }
@@ -448,15 +450,17 @@ int lb_kernel_times(lb_handle *h, const char **names, double *ms, int cap, int *
 {
     if (!h || !count) return LB_EINVAL;
     if (h->timed_launches == 0) return LB_ESTATE;
-    static const char *kNames64[2] = {"lbnr::k_moments<lbnr::D3Q19>", "lbnr::k_collide<lbnr::D3Q19>"};
-    static const char *kNames32[2] = {"lbnr::k_moments32<lbnr::D3Q19>", "lbnr::k_collide32<lbnr::D3Q19>"};
-    static const char *kNames64q9[2] = {"lbnr::k_moments<lbnr::D2Q9>", "lbnr::k_collide<lbnr::D2Q9>"};
-    static const char *kNames32q9[2] = {"lbnr::k_moments32<lbnr::D2Q9>", "lbnr::k_collide32<lbnr::D2Q9>"};
-    static const char *kFused64[1] = {"lbnr::k_fused<double>"};
-    static const char *kFused32[1] = {"lbnr::k_fused<float>"};
-    const bool q9 = h->G.nq == LB_D2Q9;
-    const char *const *kNames = h->timed_fused ? (fp32(h) ? kFused32 : kFused64)
-                                               : (fp32(h) ? (q9 ? kNames32q9 : kNames32) : (q9 ? kNames64q9 : kNames64));
+    // the kernels' own (template instance) names, as a profiler lists them
+    static const char *kMom[2][2] = {{"lbnr::k_moments<lbnr::D3Q19>", "lbnr::k_moments<lbnr::D2Q9>"},
+                                     {"lbnr::k_moments32<lbnr::D3Q19>", "lbnr::k_moments32<lbnr::D2Q9>"}};
+    static const char *kCol[2][2][2] = {
+        {{"lbnr::k_collide<lbnr::D3Q19, false>", "lbnr::k_collide<lbnr::D3Q19, true>"},
+         {"lbnr::k_collide<lbnr::D2Q9, false>", "lbnr::k_collide<lbnr::D2Q9, true>"}},
+        {{"lbnr::k_collide32<lbnr::D3Q19, false>", "lbnr::k_collide32<lbnr::D3Q19, true>"},
+         {"lbnr::k_collide32<lbnr::D2Q9, false>", "lbnr::k_collide32<lbnr::D2Q9, true>"}}};
+    static const char *kFused[2] = {"lbnr::k_fused<double>", "lbnr::k_fused<float>"};
+    const int f32 = fp32(h) ? 1 : 0, q9 = h->G.nq == LB_D2Q9 ? 1 : 0, mat = h->timed_matter ? 1 : 0;
+    const char *kNames[2] = {h->timed_fused ? kFused[f32] : kMom[f32][q9], kCol[f32][q9][mat]};
     const int nk = h->timed_fused ? 1 : 2;
     const double vals[2] = {h->ms_moments, h->ms_collide};
     int n = 0;

@@ -146,7 +146,7 @@ def test_fp32_error_norms_and_kernel_names():
         g.init_fields(u0)
         g.set_timing(True)
         g.step(2)
-        assert set(g.kernel_times()) == {"lbnr::k_moments32<lbnr::D3Q19>", "lbnr::k_collide32<lbnr::D3Q19>"}
+        assert set(g.kernel_times()) == {"lbnr::k_moments32<lbnr::D3Q19>", "lbnr::k_collide32<lbnr::D3Q19, false>"}
         u = g.moments()
         nr = g.error_norms(torch.from_numpy(ref).cuda())
     assert np.array_equal(nr["max_abs"], np.abs(u - ref).reshape(16, -1).max(axis=1))

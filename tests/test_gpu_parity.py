@@ -254,9 +254,9 @@ def test_kernel_timing_names_the_launched_kernels():
     from paper_1505_02037_amd import lb
 
     cases = (
-        (19, 32, 1, {"lbnr::k_moments<lbnr::D3Q19>", "lbnr::k_collide<lbnr::D3Q19>"}),
+        (19, 32, 1, {"lbnr::k_moments<lbnr::D3Q19>", "lbnr::k_collide<lbnr::D3Q19, false>"}),
         (19, 32, 2, {"lbnr::k_fused<double>"}),
-        (9, 1, 1, {"lbnr::k_moments<lbnr::D2Q9>", "lbnr::k_collide<lbnr::D2Q9>"}),
+        (9, 1, 1, {"lbnr::k_moments<lbnr::D2Q9>", "lbnr::k_collide<lbnr::D2Q9, false>"}),
     )
     for lattice, nz, path, names in cases:
         with lb.Lattice(32, 32, nz, 0.6, device=0, path=path, lattice=lattice) as g:
