@@ -1,11 +1,13 @@
 /*
- * hbm_probe.h -- a plain device-to-device copy of known size.
+ * hbm_probe.h -- plain device-to-device copies and reads of known size.
  *
  * Not part of the lattice Boltzmann method: it measures the card's achievable
- * HBM bandwidth (a copy reads and writes every byte once) and calibrates the
+ * HBM bandwidth (a copy reads and writes every byte once), calibrates the
  * HBM traffic counters (FETCH_SIZE / WRITE_SIZE of a copy of B bytes each
- * way).  The roofline figures of the method's kernels are quoted against the
- * vendor peak and against this measured ceiling.
+ * way), and tells whether a re-read of recently read data is served faster
+ * (by the Infinity Cache) than a first read.  The roofline figures of the
+ * method's kernels are quoted against the vendor peak and against these
+ * measured ceilings.
  */
 #ifndef LBNR_HBM_PROBE_H
 #define LBNR_HBM_PROBE_H
@@ -26,6 +28,13 @@ int hbm_copy_probe(size_t bytes, int reps, double *ms);
 /* Same, for a read-only stream over one buffer of `bytes` (the result of the
  * reduction is kept on the device); *ms is the average per pass. */
 int hbm_read_probe(size_t bytes, int reps, double *ms);
+
+/* Re-read test: reads a buffer of `bytes` and times an immediate second read
+ * (*ms_hot); reads it, then a separate buffer of `flush_bytes`, and times a
+ * read of the first buffer again (*ms_cold).  Best of `reps` of each, in
+ * milliseconds.  bytes and flush_bytes multiples of 64; return codes as for
+ * hbm_copy_probe. */
+int hbm_reread_probe(size_t bytes, size_t flush_bytes, int reps, double *ms_hot, double *ms_cold);
 
 #ifdef __cplusplus
 }

@@ -52,6 +52,10 @@ extern "C" {
 
 #define LB_SLICING_HARMONIC 0 /* Q = tr K  (harmonic slicing)  */
 #define LB_SLICING_GEODESIC 1 /* Q = 0     (geodesic slicing)  */
+#define LB_SLICING_ONE_PLUS_LOG 2 /* Q = tr K / alpha ("1+log" slicing; the
+                                     paper names it in section "Gauge
+                                     choices" and evaluates only the other
+                                     two: a declared variant) */
 
 #define LB_FP64 0      /* distributions stored and collided in FP64 */
 #define LB_FP32_DEV 1  /* distributions stored and streamed in FP32 as
@@ -72,7 +76,8 @@ typedef struct lb_config {
     int lattice;     /* LB_D3Q19 or LB_D2Q9 */
     int nx, ny, nz;  /* periodic extents, each >= 1 */
     double tau;      /* relaxation time in units of dt (Eq. lbe); > 1/2 */
-    int slicing;     /* LB_SLICING_HARMONIC or LB_SLICING_GEODESIC */
+    int slicing;     /* LB_SLICING_HARMONIC, LB_SLICING_GEODESIC or
+                        LB_SLICING_ONE_PLUS_LOG */
     int precision;   /* LB_FP64 or LB_FP32_DEV */
     int device;      /* HIP device ordinal, or -1 for the current device */
     void *stream;    /* hipStream_t to run on, or NULL: the library creates

@@ -21,6 +21,7 @@ from .build import LIB, build
 
 HARMONIC = 0
 GEODESIC = 1
+ONE_PLUS_LOG = 2
 D3Q19 = 19
 D2Q9 = 9
 MATTER_TENSOR = 0

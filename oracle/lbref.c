@@ -461,7 +461,11 @@ static void stage_lapse_metric(lbref *h, const double *ubar, double *ucor, doubl
         }
         full3(Kb6, Kb);
         inv3(gb, gi);
-        const double Q = (h->slicing == LBREF_SLICING_HARMONIC) ? trace_up(gi, Kb) : 0.0;
+        double Q = 0.0; /* section "Gauge choices" */
+        if (h->slicing == LBREF_SLICING_HARMONIC)
+            Q = trace_up(gi, Kb);
+        else if (h->slicing == LBREF_SLICING_ONE_PLUS_LOG)
+            Q = trace_up(gi, Kb) / ab;
         const double Ra = -(ab * ab * Q);
         FLD(R, 0, n)[x] = Ra;
         FLD(ucor, 0, n)[x] = ab + 0.5 * Ra;
@@ -621,7 +625,9 @@ int lbref_create_lattice(int lattice, int nx, int ny, int nz, double tau, int sl
     if (nx < 1 || ny < 1 || nz < 1) return LBREF_EINVAL;
     if (lattice == LBREF_D2Q9 && nz != 1) return LBREF_EINVAL;
     if (!(tau > 0.5)) return LBREF_EINVAL;
-    if (slicing != LBREF_SLICING_HARMONIC && slicing != LBREF_SLICING_GEODESIC) return LBREF_EINVAL;
+    if (slicing != LBREF_SLICING_HARMONIC && slicing != LBREF_SLICING_GEODESIC &&
+        slicing != LBREF_SLICING_ONE_PLUS_LOG)
+        return LBREF_EINVAL;
     lbref *h = (lbref *)calloc(1, sizeof(lbref));
     if (!h) return LBREF_ENOMEM;
     h->nq = lattice;
@@ -809,7 +815,11 @@ int lbref_point_rhs_matter(const double *in, int kind, const double *M, int slic
     full3(g6, g);
     full3(K6, K);
     inv3(g6, gi);
-    const double Q = (slicing == LBREF_SLICING_HARMONIC) ? trace_up(gi, K) : 0.0;
+    double Q = 0.0;
+    if (slicing == LBREF_SLICING_HARMONIC)
+        Q = trace_up(gi, K);
+    else if (slicing == LBREF_SLICING_ONE_PLUS_LOG)
+        Q = trace_up(gi, K) / alpha;
     out[0] = -(alpha * alpha * Q);
     for (int p = 0; p < 6; ++p) out[1 + p] = -2.0 * alpha * K6[p];
     bm_sources(alpha, gi, g, K, V, A, D, kind, M, S6, Om);

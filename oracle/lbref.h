@@ -35,6 +35,7 @@ extern "C" {
 
 #define LBREF_SLICING_HARMONIC 0 /* Q = tr K   (section "Gauge choices") */
 #define LBREF_SLICING_GEODESIC 1 /* Q = 0 */
+#define LBREF_SLICING_ONE_PLUS_LOG 2 /* Q = tr K / alpha ("1+log") */
 
 typedef struct lbref lbref;
 

@@ -1,5 +1,6 @@
-// hbm_probe.hip -- streaming copy of a known size (bandwidth ceiling and
-// counter calibration; see include/hbm_probe.h).
+// hbm_probe.hip -- streaming copy and reads of a known size (bandwidth
+// ceiling, counter calibration, and whether a re-read is served faster than a
+// first read; see include/hbm_probe.h).
 #include <hip/hip_runtime.h>
 
 #include "../../include/hbm_probe.h"
@@ -64,6 +65,58 @@ extern "C" int hbm_read_probe(size_t bytes, int reps, double *ms)
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(a);
+    (void)hipFree(sink);
+    return rc;
+}
+
+extern "C" int hbm_reread_probe(size_t bytes, size_t flush_bytes, int reps, double *ms_hot, double *ms_cold)
+{
+    if (!ms_hot || !ms_cold || reps < 1 || bytes == 0 || bytes % 64 || flush_bytes == 0 || flush_bytes % 64)
+        return -1;
+    void *a = nullptr, *f = nullptr;
+    double *sink = nullptr;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
+    const dim3 grid((unsigned)cus * 8), block(256);
+    if (hipMalloc(&a, bytes) != hipSuccess) return -2;
+    if (hipMalloc(&f, flush_bytes) != hipSuccess) {
+        (void)hipFree(a);
+        return -2;
+    }
+    if (hipMalloc((void **)&sink, grid.x * sizeof(double)) != hipSuccess) {
+        (void)hipFree(a);
+        (void)hipFree(f);
+        return -2;
+    }
+    int rc = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const size_t n = bytes / sizeof(double2), nf = flush_bytes / sizeof(double2);
+    float best_hot = 1e30f, best_cold = 1e30f;
+    if (hipMemset(a, 0, bytes) != hipSuccess || hipMemset(f, 0, flush_bytes) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        rc = -3;
+    } else {
+        for (int r = 0; r < reps && rc == 0; ++r) {
+            for (int cold = 0; cold < 2 && rc == 0; ++cold) {
+                // a first read of the buffer, then (cold) a read of the flush buffer, then the timed read
+                hipLaunchKernelGGL(k_read, grid, block, 0, 0, (const double2 *)a, n, sink);
+                if (cold) hipLaunchKernelGGL(k_read, grid, block, 0, 0, (const double2 *)f, nf, sink);
+                (void)hipEventRecord(e0, 0);
+                hipLaunchKernelGGL(k_read, grid, block, 0, 0, (const double2 *)a, n, sink);
+                (void)hipEventRecord(e1, 0);
+                float t = 0.f;
+                if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = -3;
+                float &best = cold ? best_cold : best_hot;
+                if (t < best) best = t;
+            }
+        }
+        *ms_hot = best_hot;
+        *ms_cold = best_cold;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(f);
     (void)hipFree(sink);
     return rc;
 }

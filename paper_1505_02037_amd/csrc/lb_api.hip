@@ -14,6 +14,12 @@
 
 using lbnr::Geom;
 
+static_assert(LB_SLICING_HARMONIC == lbnr::kSlicingHarmonic && LB_SLICING_GEODESIC == lbnr::kSlicingGeodesic &&
+                  LB_SLICING_ONE_PLUS_LOG == lbnr::kSlicingOnePlusLog,
+              "slicing codes of the C-ABI and the kernels");
+static_assert(LB_MATTER_TENSOR == lbnr::kMatterTensor && LB_MATTER_FLUID == lbnr::kMatterFluid,
+              "matter kinds of the C-ABI and the kernels");
+
 namespace {
 
 thread_local char g_last_error[256] = "";
@@ -88,7 +94,9 @@ int validate(const lb_config *c)
     const double n = (double)c->nx * (double)c->ny * (double)c->nz;
     if (n > 4294967295.0) return LB_EINVAL; // 32-bit site indices
     if (!(c->tau > 0.5) || !isfinite(c->tau)) return LB_EINVAL;
-    if (c->slicing != LB_SLICING_HARMONIC && c->slicing != LB_SLICING_GEODESIC) return LB_EINVAL;
+    if (c->slicing != LB_SLICING_HARMONIC && c->slicing != LB_SLICING_GEODESIC &&
+        c->slicing != LB_SLICING_ONE_PLUS_LOG)
+        return LB_EINVAL;
     if (c->precision != LB_FP64 && c->precision != LB_FP32_DEV) return LB_EINVAL;
     if (c->path != LB_PATH_AUTO && c->path != LB_PATH_SPLIT && c->path != LB_PATH_FUSED) return LB_EINVAL;
     return LB_OK;
@@ -118,19 +126,19 @@ bool fp32(const lb_handle *h) { return h->cfg.precision == LB_FP32_DEV; }
 // moments and corrected lapse/metric of the current state
 hipError_t run_moments(lb_handle *h)
 {
-    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    const int slicing = h->cfg.slicing;
     if (fp32(h))
-        return lbnr::launch_moments32((const float *)h->fbuf[h->cur], h->G, harmonic, h->ubar, h->lm, h->stream);
-    return lbnr::launch_moments((const double *)h->fbuf[h->cur], h->G, harmonic, h->ubar, h->lm, h->stream);
+        return lbnr::launch_moments32((const float *)h->fbuf[h->cur], h->G, slicing, h->ubar, h->lm, h->stream);
+    return lbnr::launch_moments((const double *)h->fbuf[h->cur], h->G, slicing, h->ubar, h->lm, h->stream);
 }
 
 hipError_t run_collide(lb_handle *h)
 {
-    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    const int slicing = h->cfg.slicing;
     if (fp32(h))
-        return lbnr::launch_collide32((const float *)h->fbuf[h->cur], (float *)h->fbuf[h->cur ^ 1], h->G, harmonic,
+        return lbnr::launch_collide32((const float *)h->fbuf[h->cur], (float *)h->fbuf[h->cur ^ 1], h->G, slicing,
                                       h->omega, h->srcfac, h->ubar, h->lm, h->matter, h->stream);
-    return lbnr::launch_collide((const double *)h->fbuf[h->cur], (double *)h->fbuf[h->cur ^ 1], h->G, harmonic,
+    return lbnr::launch_collide((const double *)h->fbuf[h->cur], (double *)h->fbuf[h->cur ^ 1], h->G, slicing,
                                 h->omega, h->srcfac, h->ubar, h->lm, h->matter, h->stream);
 }
 
@@ -239,11 +247,11 @@ int lb_init_fields(lb_handle *h, const double *u0, int on_device)
         LB_HIP(hipMemcpyAsync(stage, u0, ubytes, hipMemcpyHostToDevice, h->stream));
         du0 = stage;
     }
-    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    const int slicing = h->cfg.slicing;
     if (fp32(h))
-        LB_HIP(lbnr::launch_init32(G, harmonic, du0, h->lm, (float *)h->fbuf[h->cur], h->matter, h->stream));
+        LB_HIP(lbnr::launch_init32(G, slicing, du0, h->lm, (float *)h->fbuf[h->cur], h->matter, h->stream));
     else
-        LB_HIP(lbnr::launch_init(G, harmonic, du0, h->lm, (double *)h->fbuf[h->cur], h->matter, h->stream));
+        LB_HIP(lbnr::launch_init(G, slicing, du0, h->lm, (double *)h->fbuf[h->cur], h->matter, h->stream));
     // the caller may release u0 as soon as this returns
     LB_HIP(hipStreamSynchronize(h->stream));
     h->initialised = true;
@@ -258,7 +266,7 @@ int lb_step(lb_handle *h, long long nsteps)
     if (!h->initialised) return LB_ESTATE;
     if (nsteps == 0) return LB_OK;
     DeviceGuard dg(h->device);
-    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    const int slicing = h->cfg.slicing;
     if (h->fused && !h->ubar_valid) {
         // the fused step starts from the current state's moments
         LB_HIP(run_moments(h));
@@ -274,10 +282,10 @@ int lb_step(lb_handle *h, long long nsteps)
         if (h->fused) {
             if (fp32(h))
                 LB_HIP(lbnr::launch_fused32((const float *)h->fbuf[h->cur], (float *)h->fbuf[h->cur ^ 1], h->G,
-                                            harmonic, h->omega, h->srcfac, h->ubar, h->ubar2, h->stream));
+                                            slicing, h->omega, h->srcfac, h->ubar, h->ubar2, h->stream));
             else
                 LB_HIP(lbnr::launch_fused64((const double *)h->fbuf[h->cur], (double *)h->fbuf[h->cur ^ 1], h->G,
-                                            harmonic, h->omega, h->srcfac, h->ubar, h->ubar2, h->stream));
+                                            slicing, h->omega, h->srcfac, h->ubar, h->ubar2, h->stream));
             double *t = h->ubar;
             h->ubar = h->ubar2;
             h->ubar2 = t;
@@ -321,10 +329,10 @@ int lb_moments(lb_handle *h, double *u_out, int on_device)
     if (!h->initialised) return LB_ESTATE;
     DeviceGuard dg(h->device);
     const Geom &G = h->G;
-    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    const int slicing = h->cfg.slicing;
     double *dst = on_device ? u_out : spare(h);
     LB_HIP(run_moments(h));
-    LB_HIP(lbnr::launch_output(G, harmonic, h->ubar, h->lm, dst, h->matter, h->stream));
+    LB_HIP(lbnr::launch_output(G, slicing, h->ubar, h->lm, dst, h->matter, h->stream));
     if (!on_device)
         LB_HIP(hipMemcpyAsync(u_out, dst, (size_t)16 * G.nsite * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     LB_HIP(hipStreamSynchronize(h->stream));
@@ -366,13 +374,13 @@ int lb_error_norms(lb_handle *h, const double *u_ref, int on_device, double *max
     if (!h->initialised) return LB_ESTATE;
     DeviceGuard dg(h->device);
     const Geom &G = h->G;
-    const int harmonic = h->cfg.slicing == LB_SLICING_HARMONIC;
+    const int slicing = h->cfg.slicing;
     // spare buffer layout: [u 16 x nsite][ref 16 x nsite][norm scratch]
     double *u = spare(h);
     double *ref = u + (size_t)16 * G.nsite;
     double *scratch = ref + (size_t)16 * G.nsite;
     LB_HIP(run_moments(h));
-    LB_HIP(lbnr::launch_output(G, harmonic, h->ubar, h->lm, u, h->matter, h->stream));
+    LB_HIP(lbnr::launch_output(G, slicing, h->ubar, h->lm, u, h->matter, h->stream));
     const double *dref = u_ref;
     if (!on_device) {
         LB_HIP(hipMemcpyAsync(ref, u_ref, (size_t)16 * G.nsite * sizeof(double), hipMemcpyHostToDevice, h->stream));

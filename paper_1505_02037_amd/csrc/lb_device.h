@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lb_kernels.h"
+
 namespace lbnr {
 
 constexpr int kFields = 16;
@@ -114,13 +116,16 @@ __device__ __forceinline__ double trace_up(const double gi[6], const double K[6]
 //   alpha_c = abar + R_alpha/2,  gamma_c = gbar + R_gamma/2.
 // ub: the 13 raw moments alpha, gamma[6], K[6].  Out: lm[7] corrected,
 // R[7] right-hand sides.
-__device__ __forceinline__ void lapse_metric(const double ub[13], bool harmonic,
-                                             double lm[7], double R[7])
+__device__ __forceinline__ void lapse_metric(const double ub[13], int slicing, double lm[7], double R[7])
 {
     const double ab = ub[0];
     double gi[6];
     sym_inverse(ub + 1, gi);
-    const double Q = harmonic ? trace_up(gi, ub + 7) : 0.0;
+    double Q = 0.0;
+    if (slicing == kSlicingHarmonic)
+        Q = trace_up(gi, ub + 7);
+    else if (slicing == kSlicingOnePlusLog)
+        Q = trace_up(gi, ub + 7) / ab;
     const double Ra = -(ab * ab * Q);
     R[0] = Ra;
     lm[0] = ab + 0.5 * Ra;
@@ -386,9 +391,6 @@ __device__ __forceinline__ void bm_flux(double alpha, const double g[6], const d
 // With R4_ij = G_ij - gamma_ij/2 (-alpha^2 G^00 + tr G), tr G = gamma^{ij} G_ij,
 // S_ij gains gamma_ij/4 (2 alpha^2 G^00) - R4_ij (added to the vacuum value
 // as one sum) and Omega_k gains alpha (alpha G^0_k).
-constexpr int kMatterTensor = 0;
-constexpr int kMatterFluid = 1;
-
 __device__ __forceinline__ void matter_sources(double alpha, const double g[6], const double gi[6], int kind,
                                                const double M[10], double S[6], double Om[3])
 {

@@ -20,21 +20,21 @@
 namespace lbnr {
 
 template <class L>
-__global__ void __launch_bounds__(256) k_moments32(const float *__restrict__ fin, Geom G, int harmonic,
+__global__ void __launch_bounds__(256) k_moments32(const float *__restrict__ fin, Geom G, int slicing,
                                                    double *__restrict__ ubar, double *__restrict__ lm)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) moments_site32<L>(fin, G, s, harmonic, ubar, lm);
+    if (s < G.nsite) moments_site32<L>(fin, G, s, slicing, ubar, lm);
 }
 
 template <class L, bool HasMatter>
 __global__ void __launch_bounds__(256) k_collide32(const float *__restrict__ fin, float *__restrict__ fout, Geom G,
-                                                   int harmonic, double omega, double srcfac,
+                                                   int slicing, double omega, double srcfac,
                                                    const double *__restrict__ ubar, const double *__restrict__ lm,
                                                    MatterArg m)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) collide_site32<L, HasMatter>(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm, m);
+    if (s < G.nsite) collide_site32<L, HasMatter>(fin, fout, G, s, slicing, omega, srcfac, ubar, lm, m);
 }
 
 // initial deviations: d_q = f^eq_q(u0) - w_q R(u0)/2 - w_q u_rest (FP64, then rounded)
@@ -62,7 +62,7 @@ __device__ __forceinline__ void init32_field(float *__restrict__ fout, const Geo
 }
 
 template <class L, bool HasMatter>
-__global__ void __launch_bounds__(256) k_init32(Geom G, int harmonic, const double *__restrict__ u0,
+__global__ void __launch_bounds__(256) k_init32(Geom G, int slicing, const double *__restrict__ u0,
                                                 const double *__restrict__ lm, float *__restrict__ fout, MatterArg m)
 {
     SiteT<L> o;
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(256) k_init32(Geom G, int harmonic, const doub
     for (int F = 0; F < kFields; ++F) u[F] = u0[(size_t)F * G.nsite + o.s];
     Params P;
     double c[7], Rag[7];
-    lapse_metric(u, harmonic != 0, c, Rag);
+    lapse_metric(u, slicing, c, Rag);
     double A[3], D[18], gi[6], S[6], Om[3];
     stencil(G, o, lm, u[0], A, D);
     sym_inverse(u + 1, gi);
@@ -110,36 +110,36 @@ __global__ void __launch_bounds__(256) k_gather32(const float *__restrict__ fin,
 
 static inline dim3 grid32(uint32_t n) { return dim3((n + 255) / 256); }
 
-hipError_t launch_moments32(const float *fin, const Geom &G, int harmonic, double *ubar, double *lm, hipStream_t st)
+hipError_t launch_moments32(const float *fin, const Geom &G, int slicing, double *ubar, double *lm, hipStream_t st)
 {
     if (G.nq == D2Q9::Q)
-        hipLaunchKernelGGL(k_moments32<D2Q9>, grid32(G.nsite), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
+        hipLaunchKernelGGL(k_moments32<D2Q9>, grid32(G.nsite), dim3(256), 0, st, fin, G, slicing, ubar, lm);
     else
-        hipLaunchKernelGGL(k_moments32<D3Q19>, grid32(G.nsite), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
+        hipLaunchKernelGGL(k_moments32<D3Q19>, grid32(G.nsite), dim3(256), 0, st, fin, G, slicing, ubar, lm);
     return hipGetLastError();
 }
 
-hipError_t launch_collide32(const float *fin, float *fout, const Geom &G, int harmonic, double omega, double srcfac,
+hipError_t launch_collide32(const float *fin, float *fout, const Geom &G, int slicing, double omega, double srcfac,
                             const double *ubar, const double *lm, const MatterArg &m, hipStream_t st)
 {
     const dim3 grid = grid32(G.nsite), blk(256);
     const bool q9 = G.nq == D2Q9::Q, mat = m.kind >= 0;
     if (q9 && mat)
-        hipLaunchKernelGGL((k_collide32<D2Q9, true>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+        hipLaunchKernelGGL((k_collide32<D2Q9, true>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
                            lm, m);
     else if (q9)
-        hipLaunchKernelGGL((k_collide32<D2Q9, false>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+        hipLaunchKernelGGL((k_collide32<D2Q9, false>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
                            lm, m);
     else if (mat)
-        hipLaunchKernelGGL((k_collide32<D3Q19, true>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+        hipLaunchKernelGGL((k_collide32<D3Q19, true>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
                            lm, m);
     else
-        hipLaunchKernelGGL((k_collide32<D3Q19, false>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac,
+        hipLaunchKernelGGL((k_collide32<D3Q19, false>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac,
                            ubar, lm, m);
     return hipGetLastError();
 }
 
-hipError_t launch_init32(const Geom &G, int harmonic, const double *u0, double *lm, float *fout, const MatterArg &m,
+hipError_t launch_init32(const Geom &G, int slicing, const double *u0, double *lm, float *fout, const MatterArg &m,
                          hipStream_t st)
 {
     hipError_t e = launch_copy_lm(G, u0, lm, st);
@@ -147,13 +147,13 @@ hipError_t launch_init32(const Geom &G, int harmonic, const double *u0, double *
     const dim3 grid = grid32(G.nsite), blk(256);
     const bool q9 = G.nq == D2Q9::Q, mat = m.kind >= 0;
     if (q9 && mat)
-        hipLaunchKernelGGL((k_init32<D2Q9, true>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+        hipLaunchKernelGGL((k_init32<D2Q9, true>), grid, blk, 0, st, G, slicing, u0, lm, fout, m);
     else if (q9)
-        hipLaunchKernelGGL((k_init32<D2Q9, false>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+        hipLaunchKernelGGL((k_init32<D2Q9, false>), grid, blk, 0, st, G, slicing, u0, lm, fout, m);
     else if (mat)
-        hipLaunchKernelGGL((k_init32<D3Q19, true>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+        hipLaunchKernelGGL((k_init32<D3Q19, true>), grid, blk, 0, st, G, slicing, u0, lm, fout, m);
     else
-        hipLaunchKernelGGL((k_init32<D3Q19, false>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+        hipLaunchKernelGGL((k_init32<D3Q19, false>), grid, blk, 0, st, G, slicing, u0, lm, fout, m);
     return hipGetLastError();
 }
 

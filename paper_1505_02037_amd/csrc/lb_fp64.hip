@@ -29,11 +29,11 @@ namespace lbnr {
 // k_moments: zeroth moments of all fields and the corrected lapse/metric
 // ---------------------------------------------------------------------------
 template <class L>
-__global__ void __launch_bounds__(256) k_moments(const double *__restrict__ fin, Geom G, int harmonic,
+__global__ void __launch_bounds__(256) k_moments(const double *__restrict__ fin, Geom G, int slicing,
                                                  double *__restrict__ ubar, double *__restrict__ lm)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) moments_site64<L>(fin, G, s, harmonic, ubar, lm);
+    if (s < G.nsite) moments_site64<L>(fin, G, s, slicing, ubar, lm);
 }
 
 // ---------------------------------------------------------------------------
@@ -41,19 +41,19 @@ __global__ void __launch_bounds__(256) k_moments(const double *__restrict__ fin,
 // ---------------------------------------------------------------------------
 template <class L, bool HasMatter>
 __global__ void __launch_bounds__(256) k_collide(const double *__restrict__ fin, double *__restrict__ fout,
-                                                 Geom G, int harmonic, double omega, double srcfac,
+                                                 Geom G, int slicing, double omega, double srcfac,
                                                  const double *__restrict__ ubar, const double *__restrict__ lm,
                                                  MatterArg m)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) collide_site64<L, HasMatter>(fin, fout, G, s, harmonic, omega, srcfac, ubar, lm, m);
+    if (s < G.nsite) collide_site64<L, HasMatter>(fin, fout, G, s, slicing, omega, srcfac, ubar, lm, m);
 }
 
 // ---------------------------------------------------------------------------
 // k_output: the half-source moments u = ubar + R/2 into an unpadded array
 // ---------------------------------------------------------------------------
 template <bool HasMatter>
-__global__ void __launch_bounds__(256) k_output(Geom G, int harmonic, const double *__restrict__ ubar,
+__global__ void __launch_bounds__(256) k_output(Geom G, int slicing, const double *__restrict__ ubar,
                                                 const double *__restrict__ lm, double *__restrict__ u, MatterArg m)
 {
     Site o;
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) k_output(Geom G, int harmonic, const doub
 #pragma unroll
     for (int F = 0; F < kFields; ++F) ub[F] = ubar[(size_t)F * G.ps + o.s];
     Params P;
-    site_params<HasMatter>(G, o, harmonic, ub, lm, P, m);
+    site_params<HasMatter>(G, o, slicing, ub, lm, P, m);
 #pragma unroll
     for (int F = 0; F < kFields; ++F) u[(size_t)F * G.nsite + o.s] = P.u[F];
 }
@@ -98,7 +98,7 @@ __device__ __forceinline__ void init_field(double *__restrict__ fout, const Geom
 }
 
 template <class L, bool HasMatter>
-__global__ void __launch_bounds__(256) k_init(Geom G, int harmonic, const double *__restrict__ u0,
+__global__ void __launch_bounds__(256) k_init(Geom G, int slicing, const double *__restrict__ u0,
                                               const double *__restrict__ lm, double *__restrict__ fout, MatterArg m)
 {
     SiteT<L> o;
@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(256) k_init(Geom G, int harmonic, const double
     Params P;
     // R_alpha, R_gamma at u0 (the corrected values are not used: u stays u0)
     double c[7], Rag[7];
-    lapse_metric(u, harmonic != 0, c, Rag);
+    lapse_metric(u, slicing, c, Rag);
     double A[3], D[18], gi[6], S[6], Om[3];
     stencil(G, o, lm, u[0], A, D);
     sym_inverse(u + 1, gi);
@@ -213,42 +213,42 @@ __global__ void __launch_bounds__(kFields) k_norm_final(const double *__restrict
 // ---------------------------------------------------------------------------
 static inline dim3 grid_for(uint32_t n, int threads) { return dim3((n + threads - 1) / threads); }
 
-hipError_t launch_moments(const double *fin, const Geom &G, int harmonic, double *ubar, double *lm, hipStream_t st)
+hipError_t launch_moments(const double *fin, const Geom &G, int slicing, double *ubar, double *lm, hipStream_t st)
 {
     if (G.nq == D2Q9::Q)
-        hipLaunchKernelGGL(k_moments<D2Q9>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
+        hipLaunchKernelGGL(k_moments<D2Q9>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, slicing, ubar, lm);
     else
-        hipLaunchKernelGGL(k_moments<D3Q19>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, harmonic, ubar, lm);
+        hipLaunchKernelGGL(k_moments<D3Q19>, grid_for(G.nsite, 256), dim3(256), 0, st, fin, G, slicing, ubar, lm);
     return hipGetLastError();
 }
 
-hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int harmonic, double omega,
+hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int slicing, double omega,
                           double srcfac, const double *ubar, const double *lm, const MatterArg &m, hipStream_t st)
 {
     const dim3 grid = grid_for(G.nsite, 256), blk(256);
     const bool q9 = G.nq == D2Q9::Q, mat = m.kind >= 0;
     if (q9 && mat)
-        hipLaunchKernelGGL((k_collide<D2Q9, true>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+        hipLaunchKernelGGL((k_collide<D2Q9, true>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
                            lm, m);
     else if (q9)
-        hipLaunchKernelGGL((k_collide<D2Q9, false>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+        hipLaunchKernelGGL((k_collide<D2Q9, false>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
                            lm, m);
     else if (mat)
-        hipLaunchKernelGGL((k_collide<D3Q19, true>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+        hipLaunchKernelGGL((k_collide<D3Q19, true>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
                            lm, m);
     else
-        hipLaunchKernelGGL((k_collide<D3Q19, false>), grid, blk, 0, st, fin, fout, G, harmonic, omega, srcfac, ubar,
+        hipLaunchKernelGGL((k_collide<D3Q19, false>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
                            lm, m);
     return hipGetLastError();
 }
 
-hipError_t launch_output(const Geom &G, int harmonic, const double *ubar, const double *lm, double *u,
+hipError_t launch_output(const Geom &G, int slicing, const double *ubar, const double *lm, double *u,
                          const MatterArg &m, hipStream_t st)
 {
     if (m.kind >= 0)
-        hipLaunchKernelGGL(k_output<true>, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, ubar, lm, u, m);
+        hipLaunchKernelGGL(k_output<true>, grid_for(G.nsite, 256), dim3(256), 0, st, G, slicing, ubar, lm, u, m);
     else
-        hipLaunchKernelGGL(k_output<false>, grid_for(G.nsite, 256), dim3(256), 0, st, G, harmonic, ubar, lm, u, m);
+        hipLaunchKernelGGL(k_output<false>, grid_for(G.nsite, 256), dim3(256), 0, st, G, slicing, ubar, lm, u, m);
     return hipGetLastError();
 }
 
@@ -258,7 +258,7 @@ hipError_t launch_copy_lm(const Geom &G, const double *u0, double *lm, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm, double *fout, const MatterArg &m,
+hipError_t launch_init(const Geom &G, int slicing, const double *u0, double *lm, double *fout, const MatterArg &m,
                        hipStream_t st)
 {
     hipError_t e = launch_copy_lm(G, u0, lm, st);
@@ -266,13 +266,13 @@ hipError_t launch_init(const Geom &G, int harmonic, const double *u0, double *lm
     const dim3 grid = grid_for(G.nsite, 256), blk(256);
     const bool q9 = G.nq == D2Q9::Q, mat = m.kind >= 0;
     if (q9 && mat)
-        hipLaunchKernelGGL((k_init<D2Q9, true>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+        hipLaunchKernelGGL((k_init<D2Q9, true>), grid, blk, 0, st, G, slicing, u0, lm, fout, m);
     else if (q9)
-        hipLaunchKernelGGL((k_init<D2Q9, false>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+        hipLaunchKernelGGL((k_init<D2Q9, false>), grid, blk, 0, st, G, slicing, u0, lm, fout, m);
     else if (mat)
-        hipLaunchKernelGGL((k_init<D3Q19, true>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+        hipLaunchKernelGGL((k_init<D3Q19, true>), grid, blk, 0, st, G, slicing, u0, lm, fout, m);
     else
-        hipLaunchKernelGGL((k_init<D3Q19, false>), grid, blk, 0, st, G, harmonic, u0, lm, fout, m);
+        hipLaunchKernelGGL((k_init<D3Q19, false>), grid, blk, 0, st, G, slicing, u0, lm, fout, m);
     return hipGetLastError();
 }
 

@@ -114,7 +114,7 @@ __device__ __forceinline__ void fused_field(const T *__restrict__ fin, T *__rest
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_fused(const T *__restrict__ fin, T *__restrict__ fout, Geom G,
-                                                    int harmonic, double omega, double srcfac,
+                                                    int slicing, double omega, double srcfac,
                                                     const double *__restrict__ ubar_in,
                                                     double *__restrict__ ubar_out, int ntx, int nty, int ntz)
 {
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(kThreads) k_fused(const T *__restrict__ fin, T
             double ub[13], c[7], R[7];
 #pragma unroll
             for (int F = 0; F < 13; ++F) ub[F] = ubar_in[(size_t)F * G.ps + s];
-            lapse_metric(ub, harmonic != 0, c, R);
+            lapse_metric(ub, slicing, c, R);
 #pragma unroll
             for (int k = 0; k < 7; ++k) sm.lm[slot][k][r] = c[k];
         }
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(kThreads) k_fused(const T *__restrict__ fin, T
         // stencil at plane z from the region ring (same arithmetic as stencil())
         const int sm1 = wrapi(z - 1 - (z0 - 2), 3), s0 = wrapi(z - (z0 - 2), 3), sp1 = wrapi(z + 1 - (z0 - 2), 3);
         double c[7], Rag[7], A[3], D[18];
-        lapse_metric(ub, harmonic != 0, c, Rag);
+        lapse_metric(ub, slicing, c, Rag);
         {
             const int np[3] = {rc + 1, rc + kReg, rc};
             const int nm[3] = {rc - 1, rc - kReg, rc};
@@ -211,22 +211,22 @@ void fused_grid(const Geom &G, int *ntx, int *nty, int *ntz, int *blocks)
     *blocks = 8 * ((ntiles + 7) / 8);
 }
 
-hipError_t launch_fused64(const double *fin, double *fout, const Geom &G, int harmonic, double omega, double srcfac,
+hipError_t launch_fused64(const double *fin, double *fout, const Geom &G, int slicing, double omega, double srcfac,
                           const double *ubar_in, double *ubar_out, hipStream_t st)
 {
     int ntx, nty, ntz, blocks;
     fused_grid(G, &ntx, &nty, &ntz, &blocks);
-    hipLaunchKernelGGL(k_fused<double>, dim3(blocks), dim3(kThreads), 0, st, fin, fout, G, harmonic, omega, srcfac,
+    hipLaunchKernelGGL(k_fused<double>, dim3(blocks), dim3(kThreads), 0, st, fin, fout, G, slicing, omega, srcfac,
                        ubar_in, ubar_out, ntx, nty, ntz);
     return hipGetLastError();
 }
 
-hipError_t launch_fused32(const float *fin, float *fout, const Geom &G, int harmonic, double omega, double srcfac,
+hipError_t launch_fused32(const float *fin, float *fout, const Geom &G, int slicing, double omega, double srcfac,
                           const double *ubar_in, double *ubar_out, hipStream_t st)
 {
     int ntx, nty, ntz, blocks;
     fused_grid(G, &ntx, &nty, &ntz, &blocks);
-    hipLaunchKernelGGL(k_fused<float>, dim3(blocks), dim3(kThreads), 0, st, fin, fout, G, harmonic, omega, srcfac,
+    hipLaunchKernelGGL(k_fused<float>, dim3(blocks), dim3(kThreads), 0, st, fin, fout, G, slicing, omega, srcfac,
                        ubar_in, ubar_out, ntx, nty, ntz);
     return hipGetLastError();
 }

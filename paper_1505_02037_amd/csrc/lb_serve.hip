@@ -29,7 +29,7 @@ namespace lbnr {
 struct ReqDesc {
     Geom G;
     double omega, srcfac;
-    int harmonic;
+    int slicing;
     int cur;              // buffer holding the current state (device-updated)
     long long remaining;  // steps left (device-updated)
     void *f[2];
@@ -53,9 +53,9 @@ __global__ void __launch_bounds__(256) k_serve_moments(const ReqDesc *__restrict
         const uint32_t s = w.first + threadIdx.x;
         if (s >= r.G.nsite) continue;
         if constexpr (kF32)
-            moments_site32((const float *)r.f[r.cur], r.G, s, r.harmonic, r.ubar, r.lm);
+            moments_site32((const float *)r.f[r.cur], r.G, s, r.slicing, r.ubar, r.lm);
         else
-            moments_site64((const double *)r.f[r.cur], r.G, s, r.harmonic, r.ubar, r.lm);
+            moments_site64((const double *)r.f[r.cur], r.G, s, r.slicing, r.ubar, r.lm);
     }
 }
 
@@ -70,10 +70,10 @@ __global__ void __launch_bounds__(256) k_serve_collide(const ReqDesc *__restrict
         const uint32_t s = w.first + threadIdx.x;
         if (s >= r.G.nsite) continue;
         if constexpr (kF32)
-            collide_site32((const float *)r.f[r.cur], (float *)r.f[r.cur ^ 1], r.G, s, r.harmonic, r.omega,
+            collide_site32((const float *)r.f[r.cur], (float *)r.f[r.cur ^ 1], r.G, s, r.slicing, r.omega,
                            r.srcfac, r.ubar, r.lm);
         else
-            collide_site64((const double *)r.f[r.cur], (double *)r.f[r.cur ^ 1], r.G, s, r.harmonic, r.omega,
+            collide_site64((const double *)r.f[r.cur], (double *)r.f[r.cur ^ 1], r.G, s, r.slicing, r.omega,
                            r.srcfac, r.ubar, r.lm);
     }
 }
@@ -165,7 +165,8 @@ bool valid_request(const lb_config *c)
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return false;
     if ((double)c->nx * c->ny * c->nz > 4294967295.0) return false;
     if (!(c->tau > 0.5) || !isfinite(c->tau)) return false;
-    return c->slicing == LB_SLICING_HARMONIC || c->slicing == LB_SLICING_GEODESIC;
+    return c->slicing == LB_SLICING_HARMONIC || c->slicing == LB_SLICING_GEODESIC ||
+           c->slicing == LB_SLICING_ONE_PLUS_LOG;
 }
 
 // first-fit allocator over [0, size) with coalescing
@@ -329,7 +330,7 @@ int admit(lb_server *s)
         d.G = r.G;
         d.omega = 1.0 / r.cfg.tau;
         d.srcfac = 1.0 - 0.5 * d.omega;
-        d.harmonic = r.cfg.slicing == LB_SLICING_HARMONIC;
+        d.slicing = r.cfg.slicing;
         d.cur = 0;
         d.remaining = r.nsteps;
         d.f[0] = base + r.L.f0;
@@ -340,9 +341,9 @@ int admit(lb_server *s)
         double *stage = (double *)d.f[1];
         SV_HIP(hipMemcpyAsync(stage, r.u0.data(), r.u0.size() * sizeof(double), hipMemcpyHostToDevice, s->stream));
         if (f32)
-            SV_HIP(lbnr::launch_init32(r.G, d.harmonic, stage, d.lm, (float *)d.f[0], lbnr::MatterArg{}, s->stream));
+            SV_HIP(lbnr::launch_init32(r.G, d.slicing, stage, d.lm, (float *)d.f[0], lbnr::MatterArg{}, s->stream));
         else
-            SV_HIP(lbnr::launch_init(r.G, d.harmonic, stage, d.lm, (double *)d.f[0], lbnr::MatterArg{}, s->stream));
+            SV_HIP(lbnr::launch_init(r.G, d.slicing, stage, d.lm, (double *)d.f[0], lbnr::MatterArg{}, s->stream));
         SV_HIP(hipStreamSynchronize(s->stream));
         std::vector<double>().swap(r.u0);
         r.state = LB_REQ_RUNNING;
@@ -378,10 +379,10 @@ int harvest(lb_server *s)
         // finished: u = ubar + R/2 into the spare buffer, then to the host
         double *out = (double *)d.f[d.cur ^ 1];
         if (f32)
-            SV_HIP(lbnr::launch_moments32((const float *)d.f[d.cur], r.G, d.harmonic, d.ubar, d.lm, s->stream));
+            SV_HIP(lbnr::launch_moments32((const float *)d.f[d.cur], r.G, d.slicing, d.ubar, d.lm, s->stream));
         else
-            SV_HIP(lbnr::launch_moments((const double *)d.f[d.cur], r.G, d.harmonic, d.ubar, d.lm, s->stream));
-        SV_HIP(lbnr::launch_output(r.G, d.harmonic, d.ubar, d.lm, out, lbnr::MatterArg{}, s->stream));
+            SV_HIP(lbnr::launch_moments((const double *)d.f[d.cur], r.G, d.slicing, d.ubar, d.lm, s->stream));
+        SV_HIP(lbnr::launch_output(r.G, d.slicing, d.ubar, d.lm, out, lbnr::MatterArg{}, s->stream));
         r.result.resize((size_t)16 * r.G.nsite);
         SV_HIP(hipMemcpyAsync(r.result.data(), out, r.result.size() * sizeof(double), hipMemcpyDeviceToHost,
                               s->stream));

@@ -122,12 +122,12 @@ __device__ __forceinline__ void params_from(const double ub[kFields], const doub
 }
 
 template <bool HasMatter = false, class L>
-__device__ __forceinline__ void site_params(const Geom &G, const SiteT<L> &o, int harmonic,
+__device__ __forceinline__ void site_params(const Geom &G, const SiteT<L> &o, int slicing,
                                             const double ub[kFields], const double *__restrict__ lm,
                                             Params &P, const MatterArg &m = MatterArg{})
 {
     double c[7], Rag[7], A[3], D[18];
-    lapse_metric(ub, harmonic != 0, c, Rag);
+    lapse_metric(ub, slicing, c, Rag);
     stencil(G, o, lm, c[0], A, D);
     if constexpr (HasMatter) {
         double M[10];

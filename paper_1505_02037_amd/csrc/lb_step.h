@@ -42,7 +42,7 @@ __device__ __forceinline__ double plane_sum(const T *__restrict__ fin, const Geo
 // zeroth moments of all fields at site s and its corrected lapse/metric
 template <class L = D3Q19>
 __device__ __forceinline__ void moments_site64(const double *__restrict__ fin, const Geom &G, uint32_t s,
-                                               int harmonic, double *__restrict__ ubar, double *__restrict__ lm)
+                                               int slicing, double *__restrict__ ubar, double *__restrict__ lm)
 {
     SiteT<L> o;
     site_of(G, s, o);
@@ -53,7 +53,7 @@ __device__ __forceinline__ void moments_site64(const double *__restrict__ fin, c
         ub[F] = plane_sum<double>(fin, G, F, o);
     }
     double c[7], R[7];
-    lapse_metric(ub, harmonic != 0, c, R);
+    lapse_metric(ub, slicing, c, R);
 #pragma unroll
     for (int F = 0; F < kFields; ++F) ubar[(size_t)F * G.ps + o.s] = ub[F];
 #pragma unroll
@@ -120,7 +120,7 @@ __device__ __forceinline__ void collide_all(const double *__restrict__ fin, doub
 // sources, flux, BGK relaxation with source and pull streaming at site s
 template <class L = D3Q19, bool HasMatter = false>
 __device__ __forceinline__ void collide_site64(const double *__restrict__ fin, double *__restrict__ fout,
-                                               const Geom &G, uint32_t s, int harmonic, double omega,
+                                               const Geom &G, uint32_t s, int slicing, double omega,
                                                double srcfac, const double *__restrict__ ubar,
                                                const double *__restrict__ lm, const MatterArg &m = MatterArg{})
 {
@@ -130,7 +130,7 @@ __device__ __forceinline__ void collide_site64(const double *__restrict__ fin, d
 #pragma unroll
     for (int F = 0; F < kFields; ++F) ub[F] = ubar[(size_t)F * G.ps + o.s];
     Params P;
-    site_params<HasMatter>(G, o, harmonic, ub, lm, P, m);
+    site_params<HasMatter>(G, o, slicing, ub, lm, P, m);
     pull_sources(G, o);
     collide_all<0>(fin, fout, G, o, P, omega, srcfac);
 }
@@ -145,7 +145,7 @@ __host__ __device__ constexpr float wqf(int q) { return (float)L::w(q); }
 
 template <class L = D3Q19>
 __device__ __forceinline__ void moments_site32(const float *__restrict__ fin, const Geom &G, uint32_t s,
-                                               int harmonic, double *__restrict__ ubar, double *__restrict__ lm)
+                                               int slicing, double *__restrict__ ubar, double *__restrict__ lm)
 {
     SiteT<L> o;
     site_of(G, s, o);
@@ -156,7 +156,7 @@ __device__ __forceinline__ void moments_site32(const float *__restrict__ fin, co
         ub[F] = urest(F) + plane_sum<float>(fin, G, F, o);
     }
     double c[7], R[7];
-    lapse_metric(ub, harmonic != 0, c, R);
+    lapse_metric(ub, slicing, c, R);
 #pragma unroll
     for (int F = 0; F < kFields; ++F) ubar[(size_t)F * G.ps + o.s] = ub[F];
 #pragma unroll
@@ -218,7 +218,7 @@ __device__ __forceinline__ void collide32_all(const float *__restrict__ fin, flo
 
 template <class L = D3Q19, bool HasMatter = false>
 __device__ __forceinline__ void collide_site32(const float *__restrict__ fin, float *__restrict__ fout,
-                                               const Geom &G, uint32_t s, int harmonic, double omega,
+                                               const Geom &G, uint32_t s, int slicing, double omega,
                                                double srcfac, const double *__restrict__ ubar,
                                                const double *__restrict__ lm, const MatterArg &m = MatterArg{})
 {
@@ -228,7 +228,7 @@ __device__ __forceinline__ void collide_site32(const float *__restrict__ fin, fl
 #pragma unroll
     for (int F = 0; F < kFields; ++F) ub[F] = ubar[(size_t)F * G.ps + o.s];
     Params P;
-    site_params<HasMatter>(G, o, harmonic, ub, lm, P, m);
+    site_params<HasMatter>(G, o, slicing, ub, lm, P, m);
     pull_sources(G, o);
     collide32_all<0>(fin, fout, G, o, P, (float)omega, srcfac);
 }

@@ -29,6 +29,7 @@ D3Q19 = LB_D3Q19
 D2Q9 = LB_D2Q9
 HARMONIC = 0
 GEODESIC = 1
+ONE_PLUS_LOG = 2
 FP64 = 0
 FP32_DEV = 1
 PATH_AUTO = 0

@@ -64,8 +64,8 @@ def compiled(name: str):
         + [D[k][i][j] for k in range(3) for i, j in PAIRS]
     dt = [sp.diff(a, t)] + [sp.diff(g[i, j], t) for i, j in PAIRS] \
         + [sp.diff(K[i, j], t) for i, j in PAIRS] + [sp.diff(v, t) for v in V]
-    fs = sp.lambdify((t, x1, x2, x3), state, modules="mpmath")
-    fd = sp.lambdify((t, x1, x2, x3), dt, modules="mpmath")
+    fs = sp.lambdify((t, x1, x2, x3), state, modules="mpmath", cse=True)
+    fd = sp.lambdify((t, x1, x2, x3), dt, modules="mpmath", cse=True)
     return sol, fs, fd
 
 
@@ -241,20 +241,37 @@ def flrw_dust_sheared() -> Solution:
     return _shear_solution(flrw(sp.Integer(0)), "flrw_dust_sheared", ((1.4, -0.5, 0.2, 0.1),))
 
 
+def _manufactured_metric():
+    h = sp.Matrix([
+        [sp.sin(x1 + t) / 8, sp.cos(x2 - 2 * t) / 15, sp.sin(x3 + x1) / 17],
+        [0, sp.cos(x1 + x3 + t / 2) / 9, sp.sin(x2 - t) / 13],
+        [0, 0, sp.sin(x1 - x2 + x3 + t) / 11],
+    ])
+    return sp.eye(3) + sp.Matrix(3, 3, lambda i, j: h[min(i, j), max(i, j)])
+
+
 def manufactured() -> Solution:
     """A generic zero-shift metric (lapse and all six metric components vary
     in space and time).  Its Einstein tensor is a general energy-momentum
     tensor: energy density, momentum density G^0_k and anisotropic stresses
     are all non-zero."""
     a = 1 + sp.Rational(1, 10) * sp.sin(x1 + 2 * x2 - t / 3) + sp.Rational(1, 20) * sp.cos(x3 - t)
-    h = sp.Matrix([
-        [sp.sin(x1 + t) / 8, sp.cos(x2 - 2 * t) / 15, sp.sin(x3 + x1) / 17],
-        [0, sp.cos(x1 + x3 + t / 2) / 9, sp.sin(x2 - t) / 13],
-        [0, 0, sp.sin(x1 - x2 + x3 + t) / 11],
-    ])
-    g = sp.eye(3) + sp.Matrix(3, 3, lambda i, j: h[min(i, j), max(i, j)])
+    g = _manufactured_metric()
     return Solution("manufactured", a, g, g.inv(method="ADJ"), None,
                     ((0.3, 0.2, -0.4, 0.7), (1.1, -0.9, 0.5, 0.2)))
+
+
+def manufactured_slicing(kind: str) -> Solution:
+    """The manufactured metric with a lapse that satisfies a slicing
+    condition.  With zero shift tr K = -d_t ln sqrt(det gamma) / alpha, so
+    d_t alpha = -alpha^2 Q holds for
+      harmonic (Q = tr K):          alpha = sqrt(det gamma),
+      "1+log"  (Q = tr K / alpha):  alpha = 1 + ln sqrt(det gamma)."""
+    g = _manufactured_metric()
+    root = sp.sqrt(g.det(method="berkowitz"))
+    a = root if kind == "harmonic" else 1 + sp.log(root)
+    return Solution(f"manufactured_{kind}", a, g, g.inv(method="ADJ"), kind,
+                    ((0.3, 0.2, -0.4, 0.7),))
 
 
 MATTER_SOLUTIONS = {
@@ -263,6 +280,8 @@ MATTER_SOLUTIONS = {
     "flrw_stiff_sheared": flrw_stiff_sheared,
     "flrw_dust_sheared": flrw_dust_sheared,
     "manufactured": manufactured,
+    "manufactured_harmonic": lambda: manufactured_slicing("harmonic"),
+    "manufactured_1+log": lambda: manufactured_slicing("1+log"),
 }
 SOLUTIONS.update(MATTER_SOLUTIONS)
 
@@ -281,9 +300,9 @@ def _metric_derivatives(name: str):
     comps = [(a, b) for a in range(4) for b in range(a, 4)]
     d1 = [[sp.diff(g4[a, b], C[c]) for (a, b) in comps] for c in range(4)]
     d2 = [[[sp.diff(g4[a, b], C[c], C[d]) for (a, b) in comps] for d in range(4)] for c in range(4)]
-    f0 = sp.lambdify(C, [g4[a, b] for (a, b) in comps], modules="mpmath")
-    f1 = sp.lambdify(C, d1, modules="mpmath")
-    f2 = sp.lambdify(C, d2, modules="mpmath")
+    f0 = sp.lambdify(C, [g4[a, b] for (a, b) in comps], modules="mpmath", cse=True)
+    f1 = sp.lambdify(C, d1, modules="mpmath", cse=True)
+    f2 = sp.lambdify(C, d2, modules="mpmath", cse=True)
     return comps, f0, f1, f2
 
 

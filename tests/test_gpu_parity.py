@@ -79,6 +79,8 @@ CASES = [
     # several 14 x 14 tiles with ragged edges, two z-chunks (64 + 6 planes)
     ("random_33x29x70", (70, 29, 33), 0.7, oracle.HARMONIC, 7),
     ("random_geodesic_28x15x3", (3, 15, 28), 0.9, oracle.GEODESIC, 8),
+    # the "1+log" slicing variant (Q = tr K / alpha)
+    ("random_1pluslog_21x10x7", (7, 10, 21), 0.8, oracle.ONE_PLUS_LOG, 9),
 ]
 PATHS = {"split": 1, "fused": 2}
 
@@ -128,6 +130,7 @@ CASES_D2Q9 = [
     ("d2q9_random_geodesic_300x3", (1, 3, 300), 0.9, oracle.GEODESIC, 42),
     ("d2q9_random_1x17", (1, 17, 1), 0.8, oracle.HARMONIC, 43),
     ("d2q9_random_2x1", (1, 1, 2), 0.6, oracle.HARMONIC, 44),
+    ("d2q9_random_1pluslog_23x19", (1, 19, 23), 0.9, oracle.ONE_PLUS_LOG, 45),
 ]
 
 
