@@ -70,6 +70,18 @@ extern "C" {
 #define LB_PATH_FUSED 2  /* one z-marching launch per step that also forms
                             the next step's moments (same results) */
 
+#define LB_COLLISION_BGK 0          /* BGK with source (Eq. numlb) */
+#define LB_COLLISION_REGULARIZED 1  /* declared variant, not the paper's: of
+                                       the non-equilibrium part f - f^eq only
+                                       its zeroth and first moments are kept
+                                       and relaxed as BGK relaxes them,
+                                       f* = f^eq + (1 - 1/tau) w (m0 + c.J/c_s^2)
+                                          + w (1 - 1/(2 tau)) R;
+                                       same moments and first-order dynamics,
+                                       no higher non-equilibrium moments (the
+                                       paper suggests a stabilised collision
+                                       without specifying one); split path */
+
 typedef struct lb_handle lb_handle; /* opaque, owned by the library */
 
 typedef struct lb_config {
@@ -84,6 +96,7 @@ typedef struct lb_config {
                         and owns a stream of default priority */
     int path;        /* LB_PATH_AUTO, LB_PATH_SPLIT or LB_PATH_FUSED: how a
                         step is launched; every path gives identical results */
+    int collision;   /* LB_COLLISION_BGK (0) or LB_COLLISION_REGULARIZED */
 } lb_config;
 
 /* Allocates two distribution buffers and per-site scratch on the device.

@@ -26,6 +26,8 @@ D3Q19 = 19
 D2Q9 = 9
 MATTER_TENSOR = 0
 MATTER_FLUID = 1
+COLLISION_BGK = 0
+COLLISION_REGULARIZED = 1
 NF = 16
 NQ = 19
 
@@ -63,6 +65,7 @@ def _load():
     lib.lbref_point_rhs.argtypes = [dp, ctypes.c_int, dp]
     lib.lbref_point_rhs_matter.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, dp]
     lib.lbref_set_matter.argtypes = [P, ctypes.c_int, dp, ctypes.c_int]
+    lib.lbref_set_collision.argtypes = [P, ctypes.c_int]
     lib.lbref_point_feq.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
     lib.lbref_point_feq.restype = None
     lib.lbref_num_threads.argtypes = []
@@ -82,7 +85,8 @@ def _check(rc: int, what: str) -> None:
 class Oracle:
     """One periodic lattice evolved by the CPU oracle."""
 
-    def __init__(self, nx: int, ny: int, nz: int, tau: float, slicing: int = HARMONIC, lattice: int = D3Q19):
+    def __init__(self, nx: int, ny: int, nz: int, tau: float, slicing: int = HARMONIC, lattice: int = D3Q19,
+                 collision: int = COLLISION_BGK):
         lib = _load()
         self._lib = lib
         self.shape = (nz, ny, nx)
@@ -92,6 +96,7 @@ class Oracle:
         _check(lib.lbref_create_lattice(int(lattice), nx, ny, nz, float(tau), int(slicing), ctypes.byref(h)),
                "create")
         self._h = h
+        _check(lib.lbref_set_collision(h, int(collision)), "set_collision")
 
     def close(self) -> None:
         if self._h:

@@ -99,6 +99,7 @@ struct lbref {
     size_t nsite;
     double tau, omega, srcfac;
     int slicing;
+    int collision; /* LBREF_COLLISION_BGK or LBREF_COLLISION_REGULARIZED */
     long long nstep;
     double *f;     /* [NF][nq][nsite] current distributions */
     double *fpost; /* [NF][nq][nsite] post-collision scratch */
@@ -577,7 +578,8 @@ static double feq_at(const lbref *h, int F, int q, size_t c)
     return h->w[q] * u;
 }
 
-/* stage 4: BGK collision with source (Eq. numlb), then periodic streaming */
+/* stage 4: BGK collision with source (Eq. numlb), or its regularized
+ * variant, then periodic streaming */
 static void stage_collide_stream(lbref *h)
 {
     const size_t n = h->nsite;
@@ -587,6 +589,25 @@ static void stage_collide_stream(lbref *h)
         const size_t c = (size_t)ss;
         for (int F = 0; F < NF; ++F) {
             const double hR = srcfac * FLD(h->R, F, n)[c];
+            if (h->collision == LBREF_COLLISION_REGULARIZED) {
+                /* the non-equilibrium part keeps only its zeroth and first
+                 * moments, m0 = sum_q (f - feq) and J = sum_q c_q (f - feq),
+                 * and relaxes them as BGK does: f* = feq + (1 - omega) w
+                 * (m0 + c.J / c_s^2) + w (1 - omega/2) R */
+                double m0 = 0.0, J[3] = {0.0, 0.0, 0.0};
+                for (int q = 0; q < h->nq; ++q) {
+                    const double ne = DIST(h->f, F, q, n)[c] - feq_at(h, F, q, c);
+                    m0 += ne;
+                    for (int m = 0; m < 3; ++m) J[m] += (double)h->cq[q][m] * ne;
+                }
+                for (int q = 0; q < h->nq; ++q) {
+                    double cJ = 0.0;
+                    for (int m = 0; m < 3; ++m) cJ += (double)h->cq[q][m] * J[m];
+                    DIST(h->fpost, F, q, n)[c] =
+                        feq_at(h, F, q, c) + (1.0 - omega) * h->w[q] * (m0 + 3.0 * cJ) + h->w[q] * hR;
+                }
+                continue;
+            }
             for (int q = 0; q < h->nq; ++q) {
                 const double f = DIST(h->f, F, q, n)[c];
                 const double feq = feq_at(h, F, q, c);
@@ -749,6 +770,13 @@ int lbref_set_distributions(lbref *h, const double *f_in)
 }
 
 long long lbref_nsteps_done(const lbref *h) { return h ? h->nstep : -1; }
+
+int lbref_set_collision(lbref *h, int kind)
+{
+    if (!h || (kind != LBREF_COLLISION_BGK && kind != LBREF_COLLISION_REGULARIZED)) return LBREF_EINVAL;
+    h->collision = kind;
+    return LBREF_OK;
+}
 
 int lbref_set_matter(lbref *h, int kind, const double *M, int per_site)
 {

@@ -63,6 +63,17 @@ int lbref_set_distributions(lbref *h, const double *f_in);
 
 long long lbref_nsteps_done(const lbref *h);
 
+/* Collision: LBREF_COLLISION_BGK (Eq. numlb, the default) or the declared
+ * variant LBREF_COLLISION_REGULARIZED, which keeps of the non-equilibrium part
+ * f - f^eq only its zeroth and first moments (relaxed as BGK relaxes them):
+ *   f* = f^eq + (1 - omega) w_q (m0 + c_q.J / c_s^2) + w_q (1 - omega/2) R,
+ *   m0 = sum_q (f - f^eq),  J = sum_q c_q (f - f^eq).
+ * The paper suggests a stabilised collision (an entropic one) without
+ * specifying it; this variant is not the paper's method. */
+#define LBREF_COLLISION_BGK 0
+#define LBREF_COLLISION_REGULARIZED 1
+int lbref_set_collision(lbref *h, int kind);
+
 /* Matter (energy-momentum tensor G, units c = 8 pi G = 1; section
  * "Bona-Masso evolution equations"), in lattice units, of one of two kinds:
  *   LBREF_MATTER_TENSOR: 10 values, G^00, G^0_k (x, y, z), G_ij (xx, xy, xz,

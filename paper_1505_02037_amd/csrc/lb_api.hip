@@ -19,6 +19,8 @@ static_assert(LB_SLICING_HARMONIC == lbnr::kSlicingHarmonic && LB_SLICING_GEODES
               "slicing codes of the C-ABI and the kernels");
 static_assert(LB_MATTER_TENSOR == lbnr::kMatterTensor && LB_MATTER_FLUID == lbnr::kMatterFluid,
               "matter kinds of the C-ABI and the kernels");
+static_assert(LB_COLLISION_BGK == lbnr::kCollisionBgk && LB_COLLISION_REGULARIZED == lbnr::kCollisionRegularized,
+              "collision kinds of the C-ABI and the kernels");
 
 namespace {
 
@@ -99,6 +101,9 @@ int validate(const lb_config *c)
         return LB_EINVAL;
     if (c->precision != LB_FP64 && c->precision != LB_FP32_DEV) return LB_EINVAL;
     if (c->path != LB_PATH_AUTO && c->path != LB_PATH_SPLIT && c->path != LB_PATH_FUSED) return LB_EINVAL;
+    if (c->collision != LB_COLLISION_BGK && c->collision != LB_COLLISION_REGULARIZED) return LB_EINVAL;
+    // the z-marching launch relaxes with BGK only
+    if (c->collision != LB_COLLISION_BGK && c->path == LB_PATH_FUSED) return LB_EINVAL;
     return LB_OK;
 }
 
@@ -137,9 +142,9 @@ hipError_t run_collide(lb_handle *h)
     const int slicing = h->cfg.slicing;
     if (fp32(h))
         return lbnr::launch_collide32((const float *)h->fbuf[h->cur], (float *)h->fbuf[h->cur ^ 1], h->G, slicing,
-                                      h->omega, h->srcfac, h->ubar, h->lm, h->matter, h->stream);
+                                      h->omega, h->srcfac, h->ubar, h->lm, h->matter, h->cfg.collision, h->stream);
     return lbnr::launch_collide((const double *)h->fbuf[h->cur], (double *)h->fbuf[h->cur ^ 1], h->G, slicing,
-                                h->omega, h->srcfac, h->ubar, h->lm, h->matter, h->stream);
+                                h->omega, h->srcfac, h->ubar, h->lm, h->matter, h->cfg.collision, h->stream);
 }
 
 void free_all(lb_handle *h)
@@ -461,14 +466,19 @@ int lb_kernel_times(lb_handle *h, const char **names, double *ms, int cap, int *
     // the kernels' own (template instance) names, as a profiler lists them
     static const char *kMom[2][2] = {{"lbnr::k_moments<lbnr::D3Q19>", "lbnr::k_moments<lbnr::D2Q9>"},
                                      {"lbnr::k_moments32<lbnr::D3Q19>", "lbnr::k_moments32<lbnr::D2Q9>"}};
-    static const char *kCol[2][2][2] = {
-        {{"lbnr::k_collide<lbnr::D3Q19, false>", "lbnr::k_collide<lbnr::D3Q19, true>"},
-         {"lbnr::k_collide<lbnr::D2Q9, false>", "lbnr::k_collide<lbnr::D2Q9, true>"}},
-        {{"lbnr::k_collide32<lbnr::D3Q19, false>", "lbnr::k_collide32<lbnr::D3Q19, true>"},
-         {"lbnr::k_collide32<lbnr::D2Q9, false>", "lbnr::k_collide32<lbnr::D2Q9, true>"}}};
+    static const char *kCol[2][2][2][2] = {
+        {{{"lbnr::k_collide<lbnr::D3Q19, false, 0>", "lbnr::k_collide<lbnr::D3Q19, false, 1>"},
+          {"lbnr::k_collide<lbnr::D3Q19, true, 0>", "lbnr::k_collide<lbnr::D3Q19, true, 1>"}},
+         {{"lbnr::k_collide<lbnr::D2Q9, false, 0>", "lbnr::k_collide<lbnr::D2Q9, false, 1>"},
+          {"lbnr::k_collide<lbnr::D2Q9, true, 0>", "lbnr::k_collide<lbnr::D2Q9, true, 1>"}}},
+        {{{"lbnr::k_collide32<lbnr::D3Q19, false, 0>", "lbnr::k_collide32<lbnr::D3Q19, false, 1>"},
+          {"lbnr::k_collide32<lbnr::D3Q19, true, 0>", "lbnr::k_collide32<lbnr::D3Q19, true, 1>"}},
+         {{"lbnr::k_collide32<lbnr::D2Q9, false, 0>", "lbnr::k_collide32<lbnr::D2Q9, false, 1>"},
+          {"lbnr::k_collide32<lbnr::D2Q9, true, 0>", "lbnr::k_collide32<lbnr::D2Q9, true, 1>"}}}};
     static const char *kFused[2] = {"lbnr::k_fused<double>", "lbnr::k_fused<float>"};
     const int f32 = fp32(h) ? 1 : 0, q9 = h->G.nq == LB_D2Q9 ? 1 : 0, mat = h->timed_matter ? 1 : 0;
-    const char *kNames[2] = {h->timed_fused ? kFused[f32] : kMom[f32][q9], kCol[f32][q9][mat]};
+    const int coll = h->cfg.collision == LB_COLLISION_REGULARIZED ? 1 : 0;
+    const char *kNames[2] = {h->timed_fused ? kFused[f32] : kMom[f32][q9], kCol[f32][q9][mat][coll]};
     const int nk = h->timed_fused ? 1 : 2;
     const double vals[2] = {h->ms_moments, h->ms_collide};
     int n = 0;

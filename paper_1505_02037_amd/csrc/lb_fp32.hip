@@ -27,14 +27,14 @@ __global__ void __launch_bounds__(256) k_moments32(const float *__restrict__ fin
     if (s < G.nsite) moments_site32<L>(fin, G, s, slicing, ubar, lm);
 }
 
-template <class L, bool HasMatter>
+template <class L, bool HasMatter, int Coll>
 __global__ void __launch_bounds__(256) k_collide32(const float *__restrict__ fin, float *__restrict__ fout, Geom G,
                                                    int slicing, double omega, double srcfac,
                                                    const double *__restrict__ ubar, const double *__restrict__ lm,
                                                    MatterArg m)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) collide_site32<L, HasMatter>(fin, fout, G, s, slicing, omega, srcfac, ubar, lm, m);
+    if (s < G.nsite) collide_site32<L, HasMatter, Coll>(fin, fout, G, s, slicing, omega, srcfac, ubar, lm, m);
 }
 
 // initial deviations: d_q = f^eq_q(u0) - w_q R(u0)/2 - w_q u_rest (FP64, then rounded)
@@ -119,23 +119,33 @@ hipError_t launch_moments32(const float *fin, const Geom &G, int slicing, double
     return hipGetLastError();
 }
 
-hipError_t launch_collide32(const float *fin, float *fout, const Geom &G, int slicing, double omega, double srcfac,
-                            const double *ubar, const double *lm, const MatterArg &m, hipStream_t st)
+template <class L, bool HasMatter>
+static void collide32_instance(int collision, dim3 grid, hipStream_t st, const float *fin, float *fout,
+                               const Geom &G, int slicing, double omega, double srcfac, const double *ubar,
+                               const double *lm, const MatterArg &m)
 {
-    const dim3 grid = grid32(G.nsite), blk(256);
+    if (collision == kCollisionRegularized)
+        hipLaunchKernelGGL((k_collide32<L, HasMatter, kCollisionRegularized>), grid, dim3(256), 0, st, fin, fout, G,
+                           slicing, omega, srcfac, ubar, lm, m);
+    else
+        hipLaunchKernelGGL((k_collide32<L, HasMatter, kCollisionBgk>), grid, dim3(256), 0, st, fin, fout, G,
+                           slicing, omega, srcfac, ubar, lm, m);
+}
+
+hipError_t launch_collide32(const float *fin, float *fout, const Geom &G, int slicing, double omega, double srcfac,
+                            const double *ubar, const double *lm, const MatterArg &m, int collision,
+                            hipStream_t st)
+{
+    const dim3 grid = grid32(G.nsite);
     const bool q9 = G.nq == D2Q9::Q, mat = m.kind >= 0;
     if (q9 && mat)
-        hipLaunchKernelGGL((k_collide32<D2Q9, true>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
-                           lm, m);
+        collide32_instance<D2Q9, true>(collision, grid, st, fin, fout, G, slicing, omega, srcfac, ubar, lm, m);
     else if (q9)
-        hipLaunchKernelGGL((k_collide32<D2Q9, false>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
-                           lm, m);
+        collide32_instance<D2Q9, false>(collision, grid, st, fin, fout, G, slicing, omega, srcfac, ubar, lm, m);
     else if (mat)
-        hipLaunchKernelGGL((k_collide32<D3Q19, true>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
-                           lm, m);
+        collide32_instance<D3Q19, true>(collision, grid, st, fin, fout, G, slicing, omega, srcfac, ubar, lm, m);
     else
-        hipLaunchKernelGGL((k_collide32<D3Q19, false>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac,
-                           ubar, lm, m);
+        collide32_instance<D3Q19, false>(collision, grid, st, fin, fout, G, slicing, omega, srcfac, ubar, lm, m);
     return hipGetLastError();
 }
 

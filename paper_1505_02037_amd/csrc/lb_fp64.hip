@@ -39,14 +39,14 @@ __global__ void __launch_bounds__(256) k_moments(const double *__restrict__ fin,
 // ---------------------------------------------------------------------------
 // k_collide: sources, flux, BGK relaxation with source, pull streaming
 // ---------------------------------------------------------------------------
-template <class L, bool HasMatter>
+template <class L, bool HasMatter, int Coll>
 __global__ void __launch_bounds__(256) k_collide(const double *__restrict__ fin, double *__restrict__ fout,
                                                  Geom G, int slicing, double omega, double srcfac,
                                                  const double *__restrict__ ubar, const double *__restrict__ lm,
                                                  MatterArg m)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < G.nsite) collide_site64<L, HasMatter>(fin, fout, G, s, slicing, omega, srcfac, ubar, lm, m);
+    if (s < G.nsite) collide_site64<L, HasMatter, Coll>(fin, fout, G, s, slicing, omega, srcfac, ubar, lm, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -222,23 +222,33 @@ hipError_t launch_moments(const double *fin, const Geom &G, int slicing, double 
     return hipGetLastError();
 }
 
-hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int slicing, double omega,
-                          double srcfac, const double *ubar, const double *lm, const MatterArg &m, hipStream_t st)
+template <class L, bool HasMatter>
+static void collide_instance(int collision, dim3 grid, hipStream_t st, const double *fin, double *fout,
+                             const Geom &G, int slicing, double omega, double srcfac, const double *ubar,
+                             const double *lm, const MatterArg &m)
 {
-    const dim3 grid = grid_for(G.nsite, 256), blk(256);
+    if (collision == kCollisionRegularized)
+        hipLaunchKernelGGL((k_collide<L, HasMatter, kCollisionRegularized>), grid, dim3(256), 0, st, fin, fout, G,
+                           slicing, omega, srcfac, ubar, lm, m);
+    else
+        hipLaunchKernelGGL((k_collide<L, HasMatter, kCollisionBgk>), grid, dim3(256), 0, st, fin, fout, G, slicing,
+                           omega, srcfac, ubar, lm, m);
+}
+
+hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int slicing, double omega,
+                          double srcfac, const double *ubar, const double *lm, const MatterArg &m, int collision,
+                          hipStream_t st)
+{
+    const dim3 grid = grid_for(G.nsite, 256);
     const bool q9 = G.nq == D2Q9::Q, mat = m.kind >= 0;
     if (q9 && mat)
-        hipLaunchKernelGGL((k_collide<D2Q9, true>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
-                           lm, m);
+        collide_instance<D2Q9, true>(collision, grid, st, fin, fout, G, slicing, omega, srcfac, ubar, lm, m);
     else if (q9)
-        hipLaunchKernelGGL((k_collide<D2Q9, false>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
-                           lm, m);
+        collide_instance<D2Q9, false>(collision, grid, st, fin, fout, G, slicing, omega, srcfac, ubar, lm, m);
     else if (mat)
-        hipLaunchKernelGGL((k_collide<D3Q19, true>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
-                           lm, m);
+        collide_instance<D3Q19, true>(collision, grid, st, fin, fout, G, slicing, omega, srcfac, ubar, lm, m);
     else
-        hipLaunchKernelGGL((k_collide<D3Q19, false>), grid, blk, 0, st, fin, fout, G, slicing, omega, srcfac, ubar,
-                           lm, m);
+        collide_instance<D3Q19, false>(collision, grid, st, fin, fout, G, slicing, omega, srcfac, ubar, lm, m);
     return hipGetLastError();
 }
 

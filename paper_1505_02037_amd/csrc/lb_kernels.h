@@ -18,6 +18,11 @@ constexpr int kSlicingOnePlusLog = 2;
 constexpr int kMatterTensor = 0;
 constexpr int kMatterFluid = 1;
 
+// Collision: BGK (Eq. numlb) or the declared regularized variant (the
+// non-equilibrium part keeps only its zeroth and first moments).
+constexpr int kCollisionBgk = 0;
+constexpr int kCollisionRegularized = 1;
+
 // Lattice geometry as the kernels see it.
 struct Geom {
     int nx, ny, nz;
@@ -40,7 +45,8 @@ struct MatterArg {
 // the gather run the lattice G.nq names
 hipError_t launch_moments(const double *fin, const Geom &G, int slicing, double *ubar, double *lm, hipStream_t st);
 hipError_t launch_collide(const double *fin, double *fout, const Geom &G, int slicing, double omega,
-                          double srcfac, const double *ubar, const double *lm, const MatterArg &m, hipStream_t st);
+                          double srcfac, const double *ubar, const double *lm, const MatterArg &m, int collision,
+                          hipStream_t st);
 hipError_t launch_output(const Geom &G, int slicing, const double *ubar, const double *lm, double *u,
                          const MatterArg &m, hipStream_t st);
 hipError_t launch_init(const Geom &G, int slicing, const double *u0, double *lm, double *fout, const MatterArg &m,
@@ -53,7 +59,8 @@ hipError_t launch_norms(const Geom &G, const double *u, const double *ref, doubl
 // FP32-deviation form (lb_fp32.hip); the output and norm kernels are shared
 hipError_t launch_moments32(const float *fin, const Geom &G, int slicing, double *ubar, double *lm, hipStream_t st);
 hipError_t launch_collide32(const float *fin, float *fout, const Geom &G, int slicing, double omega, double srcfac,
-                            const double *ubar, const double *lm, const MatterArg &m, hipStream_t st);
+                            const double *ubar, const double *lm, const MatterArg &m, int collision,
+                            hipStream_t st);
 hipError_t launch_init32(const Geom &G, int slicing, const double *u0, double *lm, float *fout, const MatterArg &m,
                          hipStream_t st);
 hipError_t launch_gather32(const float *fin, const Geom &G, int field, double *f, hipStream_t st);

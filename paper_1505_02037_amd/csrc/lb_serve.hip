@@ -161,7 +161,7 @@ Layout layout(const Geom &G, int precision)
 
 bool valid_request(const lb_config *c)
 {
-    if (!c || c->lattice != LB_D3Q19) return false;
+    if (!c || c->lattice != LB_D3Q19 || c->collision != LB_COLLISION_BGK) return false;
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return false;
     if ((double)c->nx * c->ny * c->nz > 4294967295.0) return false;
     if (!(c->tau > 0.5) || !isfinite(c->tau)) return false;

@@ -93,8 +93,46 @@ __device__ __forceinline__ void relax64(const double fl[L::Q], const Params &P, 
     relax64_q<L, Fld>(fl, P, omega, srcfac * P.R[Fld], out);
 }
 
+// Regularized variant: of the non-equilibrium part f - feq only its zeroth
+// and first moments are kept and relaxed as BGK relaxes them,
+//   out_q = feq_q + (1 - omega) w_q (m0 + c_q.J / c_s^2) + w_q (1 - omega/2) R,
+//   m0 = sum_q (f_q - feq_q),  J = sum_q c_q (f_q - feq_q)   (ascending q).
+template <class L, int Fld, int q = 0>
+__device__ __forceinline__ void feq64_all(const Params &P, double *feq)
+{
+    feq[q] = feq64<L, Fld, q>(P);
+    if constexpr (q + 1 < L::Q) feq64_all<L, Fld, q + 1>(P, feq);
+}
+
+template <class L, int q = 0>
+__device__ __forceinline__ void reg_out64(const double *feq, double a, double m0, double J0, double J1, double J2,
+                                          double hR, double *out)
+{
+    out[q] = feq[q] + a * L::w(q) * (m0 + 3.0 * cdot<q, L>(J0, J1, J2)) + L::w(q) * hR;
+    if constexpr (q + 1 < L::Q) reg_out64<L, q + 1>(feq, a, m0, J0, J1, J2, hR, out);
+}
+
+template <int Fld, class L = D3Q19>
+__device__ __forceinline__ void relax64_reg(const double fl[L::Q], const Params &P, double omega, double srcfac,
+                                            double out[L::Q])
+{
+    const double hR = srcfac * P.R[Fld];
+    double feq[L::Q];
+    feq64_all<L, Fld>(P, feq);
+    double m0 = 0.0, J0 = 0.0, J1 = 0.0, J2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        const double ne = fl[q] - feq[q];
+        m0 += ne;
+        if (L::cx(q) != 0) J0 = L::cx(q) > 0 ? J0 + ne : J0 - ne;
+        if (L::cy(q) != 0) J1 = L::cy(q) > 0 ? J1 + ne : J1 - ne;
+        if (L::cz(q) != 0) J2 = L::cz(q) > 0 ? J2 + ne : J2 - ne;
+    }
+    reg_out64<L>(feq, 1.0 - omega, m0, J0, J1, J2, hR, out);
+}
+
 // relax one field's distributions and store them at x
-template <int Fld, class L>
+template <int Fld, class L, int Coll>
 __device__ __forceinline__ void collide_field(const double *__restrict__ fin, double *__restrict__ fout,
                                               const Geom &G, const SiteT<L> &o, const Params &P,
                                               double omega, double srcfac)
@@ -102,23 +140,26 @@ __device__ __forceinline__ void collide_field(const double *__restrict__ fin, do
     double fl[L::Q], out[L::Q];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) fl[q] = plane<L>(fin, G, Fld, q)[o.src[q]];
-    relax64<Fld, L>(fl, P, omega, srcfac, out);
+    if constexpr (Coll == kCollisionRegularized)
+        relax64_reg<Fld, L>(fl, P, omega, srcfac, out);
+    else
+        relax64<Fld, L>(fl, P, omega, srcfac, out);
     // streamed: read again only by the next step's pulls
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) __builtin_nontemporal_store(out[q], &plane<L>(fout, G, Fld, q)[o.s]);
 }
 
-template <int Fld, class L>
+template <int Fld, class L, int Coll>
 __device__ __forceinline__ void collide_all(const double *__restrict__ fin, double *__restrict__ fout,
                                             const Geom &G, const SiteT<L> &o, const Params &P,
                                             double omega, double srcfac)
 {
-    collide_field<Fld>(fin, fout, G, o, P, omega, srcfac);
-    if constexpr (Fld + 1 < kFields) collide_all<Fld + 1>(fin, fout, G, o, P, omega, srcfac);
+    collide_field<Fld, L, Coll>(fin, fout, G, o, P, omega, srcfac);
+    if constexpr (Fld + 1 < kFields) collide_all<Fld + 1, L, Coll>(fin, fout, G, o, P, omega, srcfac);
 }
 
 // sources, flux, BGK relaxation with source and pull streaming at site s
-template <class L = D3Q19, bool HasMatter = false>
+template <class L = D3Q19, bool HasMatter = false, int Coll = kCollisionBgk>
 __device__ __forceinline__ void collide_site64(const double *__restrict__ fin, double *__restrict__ fout,
                                                const Geom &G, uint32_t s, int slicing, double omega,
                                                double srcfac, const double *__restrict__ ubar,
@@ -132,7 +173,7 @@ __device__ __forceinline__ void collide_site64(const double *__restrict__ fin, d
     Params P;
     site_params<HasMatter>(G, o, slicing, ub, lm, P, m);
     pull_sources(G, o);
-    collide_all<0>(fin, fout, G, o, P, omega, srcfac);
+    collide_all<0, L, Coll>(fin, fout, G, o, P, omega, srcfac);
 }
 
 // ---------------------------------------------------------------------------
@@ -203,20 +244,67 @@ __device__ __forceinline__ void relax32(const float fl[L::Q], const Params &P, f
     relax32_q<L, isK>(fl, du, hR, F0, F1, F2, om, out);
 }
 
-template <int Fld, class L>
+// regularized variant in FP32 on the deviations (see relax64_reg)
+template <class L, bool isK, int q = 0>
+__device__ __forceinline__ void deq32_all(float du, float F0, float F1, float F2, float *deq)
+{
+    if constexpr (isK)
+        deq[q] = wqf<L>(q) * (du + 3.0f * cdotf<q, L>(F0, F1, F2));
+    else
+        deq[q] = wqf<L>(q) * du;
+    if constexpr (q + 1 < L::Q) deq32_all<L, isK, q + 1>(du, F0, F1, F2, deq);
+}
+
+template <class L, int q = 0>
+__device__ __forceinline__ void reg_out32(const float *deq, float a, float m0, float J0, float J1, float J2, float hR,
+                                          float *out)
+{
+    out[q] = deq[q] + a * wqf<L>(q) * (m0 + 3.0f * cdotf<q, L>(J0, J1, J2)) + wqf<L>(q) * hR;
+    if constexpr (q + 1 < L::Q) reg_out32<L, q + 1>(deq, a, m0, J0, J1, J2, hR, out);
+}
+
+template <int Fld, class L = D3Q19>
+__device__ __forceinline__ void relax32_reg(const float fl[L::Q], const Params &P, float om, double srcfac,
+                                            float out[L::Q])
+{
+    constexpr bool isK = (Fld >= 7 && Fld <= 12);
+    constexpr int pk = isK ? Fld - 7 : 0;
+    const float du = (float)(P.u[Fld] - urest(Fld));
+    const float hR = (float)(srcfac * P.R[Fld]);
+    const float F0 = isK ? (float)P.F[pk] : 0.0f;
+    const float F1 = isK ? (float)P.F[6 + pk] : 0.0f;
+    const float F2 = isK ? (float)P.F[12 + pk] : 0.0f;
+    float deq[L::Q];
+    deq32_all<L, isK>(du, F0, F1, F2, deq);
+    float m0 = 0.0f, J0 = 0.0f, J1 = 0.0f, J2 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        const float ne = fl[q] - deq[q];
+        m0 += ne;
+        if (L::cx(q) != 0) J0 = L::cx(q) > 0 ? J0 + ne : J0 - ne;
+        if (L::cy(q) != 0) J1 = L::cy(q) > 0 ? J1 + ne : J1 - ne;
+        if (L::cz(q) != 0) J2 = L::cz(q) > 0 ? J2 + ne : J2 - ne;
+    }
+    reg_out32<L>(deq, 1.0f - om, m0, J0, J1, J2, hR, out);
+}
+
+template <int Fld, class L, int Coll>
 __device__ __forceinline__ void collide32_all(const float *__restrict__ fin, float *__restrict__ fout, const Geom &G,
                                               const SiteT<L> &o, const Params &P, float om, double srcfac)
 {
     float fl[L::Q], out[L::Q];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) fl[q] = plane<L>(fin, G, Fld, q)[o.src[q]];
-    relax32<Fld, L>(fl, P, om, srcfac, out);
+    if constexpr (Coll == kCollisionRegularized)
+        relax32_reg<Fld, L>(fl, P, om, srcfac, out);
+    else
+        relax32<Fld, L>(fl, P, om, srcfac, out);
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) __builtin_nontemporal_store(out[q], &plane<L>(fout, G, Fld, q)[o.s]);
-    if constexpr (Fld + 1 < kFields) collide32_all<Fld + 1>(fin, fout, G, o, P, om, srcfac);
+    if constexpr (Fld + 1 < kFields) collide32_all<Fld + 1, L, Coll>(fin, fout, G, o, P, om, srcfac);
 }
 
-template <class L = D3Q19, bool HasMatter = false>
+template <class L = D3Q19, bool HasMatter = false, int Coll = kCollisionBgk>
 __device__ __forceinline__ void collide_site32(const float *__restrict__ fin, float *__restrict__ fout,
                                                const Geom &G, uint32_t s, int slicing, double omega,
                                                double srcfac, const double *__restrict__ ubar,
@@ -230,7 +318,7 @@ __device__ __forceinline__ void collide_site32(const float *__restrict__ fin, fl
     Params P;
     site_params<HasMatter>(G, o, slicing, ub, lm, P, m);
     pull_sources(G, o);
-    collide32_all<0>(fin, fout, G, o, P, (float)omega, srcfac);
+    collide32_all<0, L, Coll>(fin, fout, G, o, P, (float)omega, srcfac);
 }
 
 } // namespace lbnr

@@ -37,6 +37,8 @@ PATH_SPLIT = 1
 PATH_FUSED = 2
 MATTER_TENSOR = 0
 MATTER_FLUID = 1
+COLLISION_BGK = 0
+COLLISION_REGULARIZED = 1
 NF = 16
 NQ = 19
 
@@ -59,6 +61,7 @@ class LBConfig(ctypes.Structure):
         ("device", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("path", ctypes.c_int),
+        ("collision", ctypes.c_int),
     ]
 
 
@@ -134,9 +137,9 @@ def _ptr(a, nelem: int):
 
 
 def make_config(nx, ny, nz, tau, slicing=HARMONIC, precision=FP64, device=-1, stream=None,
-                path=PATH_AUTO, lattice=LB_D3Q19) -> LBConfig:
+                path=PATH_AUTO, lattice=LB_D3Q19, collision=COLLISION_BGK) -> LBConfig:
     return LBConfig(int(lattice), int(nx), int(ny), int(nz), float(tau), int(slicing), int(precision),
-                    int(device), ctypes.c_void_p(stream) if stream else None, int(path))
+                    int(device), ctypes.c_void_p(stream) if stream else None, int(path), int(collision))
 
 
 def device_bytes(nx, ny, nz, tau=0.6, precision=FP64, lattice=LB_D3Q19, path=PATH_AUTO) -> int:
@@ -149,13 +152,13 @@ class Lattice:
 
     def __init__(self, nx: int, ny: int, nz: int, tau: float, slicing: int = HARMONIC,
                  precision: int = FP64, device: int = -1, stream=None, path: int = PATH_AUTO,
-                 lattice: int = LB_D3Q19):
+                 lattice: int = LB_D3Q19, collision: int = COLLISION_BGK):
         lib = load_library()
         self._lib = lib
         self.shape = (nz, ny, nx)
         self.nsite = nx * ny * nz
         self.nq = int(lattice)
-        cfg = make_config(nx, ny, nz, tau, slicing, precision, device, stream, path, lattice)
+        cfg = make_config(nx, ny, nz, tau, slicing, precision, device, stream, path, lattice, collision)
         h = ctypes.c_void_p()
         _check(lib.lb_create(ctypes.byref(cfg), ctypes.byref(h)), "lb_create")
         self._h = h

@@ -91,6 +91,8 @@ def test_bad_configs_are_rejected_without_a_device(lib):
         lb.make_config(8, 8, 8, 0.6, lattice=7),                      # unknown lattice
         lb.make_config(8, 8, 2, 0.6, lattice=lb.D2Q9),                # D2Q9 is one site thick
         lb.make_config(8, 8, 1, 0.6, lattice=lb.D2Q9, path=lb.PATH_FUSED),  # split path only
+        lb.make_config(8, 8, 8, 0.6, collision=2),                    # unknown collision
+        lb.make_config(8, 8, 8, 0.6, collision=lb.COLLISION_REGULARIZED, path=lb.PATH_FUSED),
     ]
     for cfg in bad:
         h = ctypes.c_void_p(1234)

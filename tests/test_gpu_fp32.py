@@ -41,28 +41,31 @@ def _rel_err(u, ref):
     return num / scale
 
 
-def _fp32(shape, tau, slicing=oracle.HARMONIC, lattice=19):
+def _fp32(shape, tau, slicing=oracle.HARMONIC, lattice=19, collision=0):
     from paper_1505_02037_amd import lb
 
     nz, ny, nx = shape
-    return lb.Lattice(nx, ny, nz, tau, slicing=slicing, precision=lb.FP32_DEV, device=0, lattice=lattice)
+    return lb.Lattice(nx, ny, nz, tau, slicing=slicing, precision=lb.FP32_DEV, device=0, lattice=lattice,
+                      collision=collision)
 
 
-@pytest.mark.parametrize("shape,tau,slicing,seed,horizons,lattice", [
-    ((5, 7, 13), 0.7, oracle.HARMONIC, 1, (0, 1, 5, 10), 19),
-    ((9, 17, 33), 1.0, oracle.GEODESIC, 2, (0, 1, 10, 30), 19),
-    ((1, 3, 2), 0.9, oracle.HARMONIC, 3, (0, 2, 10), 19),
-    ((1, 29, 37), 0.8, oracle.HARMONIC, 4, (0, 1, 5, 10), 9),
-    ((1, 1, 5), 1.0, oracle.GEODESIC, 5, (0, 2, 10), 9),
+@pytest.mark.parametrize("shape,tau,slicing,seed,horizons,lattice,collision", [
+    ((5, 7, 13), 0.7, oracle.HARMONIC, 1, (0, 1, 5, 10), 19, 0),
+    ((9, 17, 33), 1.0, oracle.GEODESIC, 2, (0, 1, 10, 30), 19, 0),
+    ((1, 3, 2), 0.9, oracle.HARMONIC, 3, (0, 2, 10), 19, 0),
+    ((1, 29, 37), 0.8, oracle.HARMONIC, 4, (0, 1, 5, 10), 9, 0),
+    ((1, 1, 5), 1.0, oracle.GEODESIC, 5, (0, 2, 10), 9, 0),
+    ((5, 7, 13), 0.7, oracle.HARMONIC, 6, (0, 1, 5, 10), 19, 1),
 ])
-def test_fp32_random_state_within_bound(shape, tau, slicing, seed, horizons, lattice):
+def test_fp32_random_state_within_bound(shape, tau, slicing, seed, horizons, lattice, collision):
     _torch()
     nz, ny, nx = shape
-    print(f"[fp32] random {nx}x{ny}x{nz} tau={tau} lattice=D{2 if lattice == 9 else 3}Q{lattice}", flush=True)
+    print(f"[fp32] random {nx}x{ny}x{nz} tau={tau} lattice=D{2 if lattice == 9 else 3}Q{lattice} "
+          f"collision={collision}", flush=True)
     u0 = workloads.random_state(nx, ny, nz, seed=seed, amp=0.05)
-    o = oracle.Oracle(nx, ny, nz, tau, slicing, lattice=lattice)
+    o = oracle.Oracle(nx, ny, nz, tau, slicing, lattice=lattice, collision=collision)
     o.init_fields(u0)
-    with _fp32(shape, tau, slicing, lattice) as g:
+    with _fp32(shape, tau, slicing, lattice, collision) as g:
         g.init_fields(u0)
         done = 0
         for n in horizons:
@@ -146,7 +149,7 @@ def test_fp32_error_norms_and_kernel_names():
         g.init_fields(u0)
         g.set_timing(True)
         g.step(2)
-        assert set(g.kernel_times()) == {"lbnr::k_moments32<lbnr::D3Q19>", "lbnr::k_collide32<lbnr::D3Q19, false>"}
+        assert set(g.kernel_times()) == {"lbnr::k_moments32<lbnr::D3Q19>", "lbnr::k_collide32<lbnr::D3Q19, false, 0>"}
         u = g.moments()
         nr = g.error_norms(torch.from_numpy(ref).cuda())
     assert np.array_equal(nr["max_abs"], np.abs(u - ref).reshape(16, -1).max(axis=1))

@@ -63,14 +63,16 @@ def test_flrw_paper_setup_bitwise():
         assert abs(u[1, 0, 0, 0] / gxx - 1) < 6e-5 and abs(u[7, 0, 0, 0] / (kxx * dt) - 1) < 3e-5
 
 
-@pytest.mark.parametrize("lattice,shape,kind,seed", [
-    (19, (6, 9, 13), oracle.MATTER_TENSOR, 51),
-    (19, (5, 7, 11), oracle.MATTER_FLUID, 52),
-    (9, (1, 11, 17), oracle.MATTER_TENSOR, 53),
-    (9, (1, 6, 5), oracle.MATTER_FLUID, 54),
+@pytest.mark.parametrize("lattice,shape,kind,seed,collision", [
+    (19, (6, 9, 13), oracle.MATTER_TENSOR, 51, 0),
+    (19, (5, 7, 11), oracle.MATTER_FLUID, 52, 0),
+    (9, (1, 11, 17), oracle.MATTER_TENSOR, 53, 0),
+    (9, (1, 6, 5), oracle.MATTER_FLUID, 54, 0),
+    (19, (4, 6, 9), oracle.MATTER_TENSOR, 55, 1),
 ])
-def test_per_site_matter_bitwise(lattice, shape, kind, seed):
-    """Seeded per-site matter on a random state, harmonic slicing, 10 steps."""
+def test_per_site_matter_bitwise(lattice, shape, kind, seed, collision):
+    """Seeded per-site matter on a random state, harmonic slicing, 10 steps
+    (BGK, and once with the regularized collision)."""
     torch = _torch()
     from paper_1505_02037_amd import lb
 
@@ -78,10 +80,10 @@ def test_per_site_matter_bitwise(lattice, shape, kind, seed):
     _say(f"[matter] per-site kind={kind} lattice={lattice} {nx}x{ny}x{nz}")
     u0 = workloads.random_state(nx, ny, nz, seed=seed, amp=0.03)
     M = workloads.random_matter(nx, ny, nz, seed=seed + 100, amp=2e-3, ncomp=2 if kind else 10)
-    o = oracle.Oracle(nx, ny, nz, 0.8, oracle.HARMONIC, lattice=lattice)
+    o = oracle.Oracle(nx, ny, nz, 0.8, oracle.HARMONIC, lattice=lattice, collision=collision)
     o.set_matter(M, kind)
     o.init_fields(u0)
-    with lb.Lattice(nx, ny, nz, 0.8, device=0, lattice=lattice) as g:
+    with lb.Lattice(nx, ny, nz, 0.8, device=0, lattice=lattice, collision=collision) as g:
         g.set_matter(torch.from_numpy(M).cuda(), kind)  # device pointer
         g.init_fields(u0)
         for n in (0, 1, 4, 10):

@@ -32,24 +32,24 @@ def _torch():
     return torch
 
 
-def _gpu_lattice(shape, tau, slicing, path=0, lattice=19):
+def _gpu_lattice(shape, tau, slicing, path=0, lattice=19, collision=0):
     from paper_1505_02037_amd import lb
 
     nz, ny, nx = shape
-    return lb.Lattice(nx, ny, nz, tau, slicing=slicing, device=0, path=path, lattice=lattice)
+    return lb.Lattice(nx, ny, nz, tau, slicing=slicing, device=0, path=path, lattice=lattice, collision=collision)
 
 
 def _say(msg):
     print(msg, flush=True)
 
 
-def _both(u0, tau, slicing, horizons, path=0, lattice=19):
+def _both(u0, tau, slicing, horizons, path=0, lattice=19, collision=0):
     """Yield (n, gpu moments, gpu distributions, oracle moments, oracle distributions)."""
     shape = u0.shape[1:]
     nz, ny, nx = shape
-    o = oracle.Oracle(nx, ny, nz, tau, slicing, lattice=lattice)
+    o = oracle.Oracle(nx, ny, nz, tau, slicing, lattice=lattice, collision=collision)
     o.init_fields(u0)
-    with _gpu_lattice(shape, tau, slicing, path, lattice) as g:
+    with _gpu_lattice(shape, tau, slicing, path, lattice, collision) as g:
         g.init_fields(u0)
         done = 0
         for n in horizons:
@@ -163,6 +163,43 @@ def test_d2q9_gauge_waves_bitwise():
         _assert_equal(ug, uo, f"diagonal moments at step {n}")
 
 
+@pytest.mark.parametrize("name,shape,tau,slicing,lattice", [
+    ("reg_random_13x7x5", (5, 7, 13), 0.7, oracle.HARMONIC, 19),
+    ("reg_random_geodesic_33x17x9", (9, 17, 33), 0.55, oracle.GEODESIC, 19),
+    ("reg_d2q9_random_19x11", (1, 11, 19), 0.6, oracle.HARMONIC, 9),
+])
+def test_regularized_collision_bitwise(name, shape, tau, slicing, lattice):
+    """The declared regularized collision equals the oracle's bit for bit."""
+    _torch()
+    _say(f"[parity] {name}")
+    nz, ny, nx = shape
+    u0 = workloads.random_state(nx, ny, nz, seed=71, amp=0.05)
+    for n, ug, fg, uo, fo in _both(u0, tau, slicing, (1, 2, 10, 30), lattice=lattice,
+                                   collision=oracle.COLLISION_REGULARIZED):
+        _assert_equal(fg, fo, f"{name} distributions at step {n}")
+        _assert_equal(ug, uo, f"{name} moments at step {n}")
+
+
+def test_regularized_gauge_wave_1d_long_horizon():
+    """1D gauge wave, A = 0.01, tau = 0.6, 1000 steps with the regularized
+    collision (which outlives BGK's blow-up): equal to the oracle throughout."""
+    _torch()
+    _say("[parity] regularized gauge wave 100x1x1 tau=0.6 1000 steps")
+    u0 = workloads.gauge_wave_x(100, 1, 1, 0.01, 100.0)
+    for n, ug, fg, uo, fo in _both(u0, 0.6, oracle.HARMONIC, range(0, 1001, 200),
+                                   collision=oracle.COLLISION_REGULARIZED):
+        _assert_equal(fg, fo, f"distributions at step {n}")
+        _assert_equal(ug, uo, f"moments at step {n}")
+
+
+def test_regularized_rejected_on_fused_path():
+    _torch()
+    from paper_1505_02037_amd import lb
+
+    with pytest.raises(lb.LBError):
+        lb.Lattice(16, 16, 16, 0.8, device=0, path=lb.PATH_FUSED, collision=lb.COLLISION_REGULARIZED)
+
+
 def test_gauge_wave_3d_x_128_resolution_pieces():
     """x-wave on 64 x 8 x 8 (a 3D lattice) equals the oracle at several
     horizons at each tau of the 3D gauge-wave series."""
@@ -257,9 +294,9 @@ def test_kernel_timing_names_the_launched_kernels():
     from paper_1505_02037_amd import lb
 
     cases = (
-        (19, 32, 1, {"lbnr::k_moments<lbnr::D3Q19>", "lbnr::k_collide<lbnr::D3Q19, false>"}),
+        (19, 32, 1, {"lbnr::k_moments<lbnr::D3Q19>", "lbnr::k_collide<lbnr::D3Q19, false, 0>"}),
         (19, 32, 2, {"lbnr::k_fused<double>"}),
-        (9, 1, 1, {"lbnr::k_moments<lbnr::D2Q9>", "lbnr::k_collide<lbnr::D2Q9, false>"}),
+        (9, 1, 1, {"lbnr::k_moments<lbnr::D2Q9>", "lbnr::k_collide<lbnr::D2Q9, false, 0>"}),
     )
     for lattice, nz, path, names in cases:
         with lb.Lattice(32, 32, nz, 0.6, device=0, path=path, lattice=lattice) as g:
