@@ -15,6 +15,7 @@ for bit, as the parity tests show).
        wavelength, A = 1e-5, tau = 4.5, geodesic slicing, D3Q19
   gw   gauge wave at the paper's setup: 800 sites, A = 1e-3, tau = 4.5
   q9   D2Q9: the paper's gauge wave on its lattice, and 4096^2 throughput
+  reg  life-times of BGK and of the regularized collision (declared variant)
 
 Error measures (per field, group-scaled): max |u - ref| over the lattice,
 divided by the max-norm of the field's tensor in ref (alpha alone, gamma, K
@@ -307,10 +308,57 @@ def q9():
     return out
 
 
+def _life(torch, make_lattice, ref_at, steps, every):
+    """First checked step at which gamma_xx deviates from the wave by more
+    than 10 % of its amplitude (or the state is non-finite), and the step at
+    which it first turns non-finite."""
+    with make_lattice() as g:
+        g.init_fields(ref_at(0.0))
+        life, blow, n = None, None, 0
+        while n < steps:
+            g.step(every)
+            n += every
+            ref = ref_at(float(n))
+            u = g.moments(ref.new_empty(ref.shape))
+            finite = bool(torch.isfinite(u).all().item())
+            if not finite:
+                blow = n
+                life = life or n
+                break
+            e = (u[1] - ref[1]).abs().max().item() / (ref[1] - 1.0).abs().max().item()
+            if life is None and e > 0.10:
+                life = n
+        return life, blow
+
+
+def reg():
+    """Life-times of the BGK step and of the regularized collision (a
+    declared variant) on the gauge-wave configurations, FP64."""
+    torch = _torch()
+    out = {"experiment": "reg BGK vs regularized life-times", "runs": []}
+    cases = [
+        ("1D x-wave 100, A=0.01", 0.6, lambda t: _x_wave_dev(torch, 100, (1, 1), 0.01, 100.0, t), (100, 1, 1), 3000, 10),
+        ("1D x-wave 100, A=0.01", 0.55, lambda t: _x_wave_dev(torch, 100, (1, 1), 0.01, 100.0, t), (100, 1, 1), 3000, 10),
+        ("3D x-wave 128^3, A=0.1", 0.55, lambda t: _x_wave_dev(torch, 128, (128, 128), 0.1, 128.0, t), (128, 128, 128), 2560, 16),
+        ("3D x-wave 128^3, A=0.1", 0.6, lambda t: _x_wave_dev(torch, 128, (128, 128), 0.1, 128.0, t), (128, 128, 128), 2560, 16),
+        ("3D x-wave 128^3, A=0.1", 1.0, lambda t: _x_wave_dev(torch, 128, (128, 128), 0.1, 128.0, t), (128, 128, 128), 2560, 16),
+        ("256^3 (1,1,0) wave, A=0.1", 0.6, lambda t: _diag_dev(torch, 256, 256, 0.1, t), (256, 256, 256), 1810, 10),
+    ]
+    for name, tau, ref_at, shape, steps, every in cases:
+        row = {"case": name, "tau": tau, "steps": steps}
+        for coll, key in ((lb.COLLISION_BGK, "bgk"), (lb.COLLISION_REGULARIZED, "regularized")):
+            t0 = time.perf_counter()
+            life, blow = _life(torch, lambda: lb.Lattice(*shape, tau, device=0, collision=coll), ref_at, steps, every)
+            row[key] = {"lifetime_steps": life, "nonfinite_at": blow, "wall_s": time.perf_counter() - t0}
+        print(json.dumps(row), flush=True)
+        out["runs"].append(row)
+    return out
+
+
 def main(argv=None) -> int:
     which = (argv if argv is not None else sys.argv[1:]) or ["c1"]
     for w in which:
-        res = {"c1": c1, "c2": c2, "c2s": c2s, "c3": c3, "c5": c5, "lin": lin, "gw": gw, "q9": q9}[w]()
+        res = {"c1": c1, "c2": c2, "c2s": c2s, "c3": c3, "c5": c5, "lin": lin, "gw": gw, "q9": q9, "reg": reg}[w]()
         print(json.dumps(res), flush=True)
     return 0
 
