@@ -24,6 +24,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -41,11 +42,19 @@ ALG_BYTES_PER_SITE = {"fp64": 2 * FIELDS * Q * 8, "fp32": 2 * FIELDS * Q * 4}
 STEP_SOURCES = ("lb_device.h", "lb_fp32.hip", "lb_fp64.hip", "lb_kernels.h", "lb_site.h", "lb_step.h")
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and blank space (the device sources hold
+    no string literals), so that editing a comment keeps the hash."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the sources the timed step kernels are built from."""
+    """Hash of the code of the sources the timed step kernels are built from."""
     h = hashlib.sha256()
     for name in STEP_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_1505_02037_amd", "csrc", name), "rb").read())
+        h.update(_code_only(open(os.path.join(ROOT, "paper_1505_02037_amd", "csrc", name)).read()).encode())
     return h.hexdigest()[:16]
 
 

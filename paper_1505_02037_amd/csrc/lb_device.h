@@ -138,8 +138,8 @@ __device__ __forceinline__ void lapse_metric(const double ub[13], int slicing, d
 }
 
 // Sources of K and V (extrinsic-curvature and momentum-variable equations,
-// vacuum, zero shift) at (alpha, gamma, K, V, A, D):  S[6] (pairs i <= j) and
-// Omega[3].  D[k*6 + p] = D_k(ij).  Index conventions: first index of D is
+// zero shift; the vacuum part, matter_sources adds the energy-momentum terms)
+// at (alpha, gamma, K, V, A, D):  S[6] (pairs i <= j) and Omega[3].  D[k*6 + p] = D_k(ij).  Index conventions: first index of D is
 // the derivative index, indices raised with the inverse metric.
 __device__ __forceinline__ void bm_sources(double alpha, const double g[6], const double gi[6],
                                            const double K[6], const double V[3],
