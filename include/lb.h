@@ -161,15 +161,24 @@ int lb_error_norms(lb_handle *h, const double *u_ref, int on_device,
 /* Steps taken since lb_init_fields. */
 long long lb_steps_done(const lb_handle *h);
 
-/* Average device time in milliseconds of each kernel of the last lb_step
- * call that ran with timing enabled (lb_set_timing), measured with HIP
- * events on the handle's stream.  names[i] and ms[i] for i < *count (at most
- * cap entries).  Returns LB_ESTATE if no timed call has run. */
+/* Enables (1) or disables (0) HIP-event timing of the step kernels.  A timed
+ * lb_step records an event around every launch and synchronises the stream
+ * at its end. */
 int lb_set_timing(lb_handle *h, int enable);
+
+/* Average device time in milliseconds of each kernel of the last lb_step
+ * call that ran with timing enabled, measured with HIP events on the
+ * handle's stream.  names[i] (static strings: the kernels' template-instance
+ * names as a profiler lists them, e.g. "lbnr::k_collide<lbnr::D3Q19, false,
+ * 0>" for lattice, matter, collision) and ms[i] for i < *count (at most cap
+ * entries).  Returns LB_ESTATE if no timed call has run. */
 int lb_kernel_times(lb_handle *h, const char **names, double *ms, int cap, int *count);
 
+/* Waits for the handle's stream, frees its device memory (and its stream if
+ * the library created it).  NULL is ignored. */
 void lb_destroy(lb_handle *h);
 
+/* Static text naming an LB_* code. */
 const char *lb_strerror(int code);
 /* Text of the last HIP failure seen by this thread (empty if none). */
 const char *lb_last_error(void);

@@ -16,6 +16,7 @@ for bit, as the parity tests show).
   gw   gauge wave at the paper's setup: 800 sites, A = 1e-3, tau = 4.5
   q9   D2Q9: the paper's gauge wave on its lattice, and 4096^2 throughput
   reg  life-times of BGK and of the regularized collision (declared variant)
+  c3r  c3 with the regularized collision
 
 Error measures (per field, group-scaled): max |u - ref| over the lattice,
 divided by the max-norm of the field's tensor in ref (alpha alone, gamma, K
@@ -162,17 +163,19 @@ def c2s():
     return out
 
 
-def c3():
+def c3(collision=lb.COLLISION_BGK):
     """256^3 diagonal wave, FP64 and FP32 side by side, ten crossings."""
     torch = _torch()
     n, A, tau = 256, 0.1, 0.6
     cross = n / math.sqrt(2.0)
     steps = int(round(10 * cross))
-    checks = sorted(set([1, 2, 5, 10, 20, 50, 100, 150, 200] + [int(round(k * cross)) for k in range(1, 11)]))
-    out = {"experiment": "c3 256^3 diagonal wave", "A": A, "tau": tau, "steps": steps, "checks": []}
+    checks = sorted(set([1, 2, 5, 10, 20, 50, 100, 150, 200, 300, 400, 500, 600, 700]
+                        + [int(round(k * cross)) for k in range(1, 11)]))
+    out = {"experiment": "c3 256^3 diagonal wave", "A": A, "tau": tau, "steps": steps,
+           "collision": "regularized" if collision else "bgk", "checks": []}
     u0 = _diag_dev(torch, n, n, A, 0.0)
-    g64 = lb.Lattice(n, n, n, tau, precision=lb.FP64, device=0)
-    g32 = lb.Lattice(n, n, n, tau, precision=lb.FP32_DEV, device=0)
+    g64 = lb.Lattice(n, n, n, tau, precision=lb.FP64, device=0, collision=collision)
+    g32 = lb.Lattice(n, n, n, tau, precision=lb.FP32_DEV, device=0, collision=collision)
     g64.init_fields(u0)
     g32.init_fields(u0)
     del u0
@@ -358,7 +361,8 @@ def reg():
 def main(argv=None) -> int:
     which = (argv if argv is not None else sys.argv[1:]) or ["c1"]
     for w in which:
-        res = {"c1": c1, "c2": c2, "c2s": c2s, "c3": c3, "c5": c5, "lin": lin, "gw": gw, "q9": q9, "reg": reg}[w]()
+        res = {"c1": c1, "c2": c2, "c2s": c2s, "c3": c3, "c5": c5, "lin": lin, "gw": gw, "q9": q9, "reg": reg,
+               "c3r": lambda: c3(lb.COLLISION_REGULARIZED)}[w]()
         print(json.dumps(res), flush=True)
     return 0
 
