@@ -1,8 +1,8 @@
 """Throughput of the Bona-Masso lattice Boltzmann step on one MI355X.
 
 Workload: the 256^3 periodic lattice with the gauge wave along the (1,1,0)
-diagonal, A = 0.1, tau = 0.6, harmonic slicing, FP64 storage and arithmetic
-(the north-star 3D configuration).  One "step" is one lattice Boltzmann time
+diagonal, A = 0.1, tau = 0.6, harmonic slicing, FP64 storage and arithmetic.
+One "step" is one lattice Boltzmann time
 step over the whole lattice (moments, lapse/metric half source, derivative
 stencil, geometry and sources, flux, equilibria, BGK relaxation with source,
 pull streaming).  Inputs are resident in HBM before timing starts.
@@ -113,7 +113,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the step runs on one GPU; --gpus must be 1 "
                           "(multi-GPU sharding is described in the design notes, not built)"}))
         return 2
 

@@ -1,6 +1,6 @@
-"""Binding of the serving C-ABI (include/lb_serve.h) and a trace driver.
+"""Binding of the serving C-ABI (include/lb_serve.h) and a trace replay.
 
-The driver replays a seeded Poisson trace of independent gauge-wave
+run_trace replays a seeded Poisson trace of independent gauge-wave
 evolutions in real time: each request is submitted when its arrival time has
 passed, the server advances every resident request together one graph launch
 at a time, and finished requests are retired.  It reports the time to

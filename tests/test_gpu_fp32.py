@@ -98,7 +98,7 @@ def test_fp32_x_wave_long_horizon_at_tau_1():
 
 
 def test_fp32_diagonal_256_cubed():
-    """The benchmark spec's 3D configuration in the FP32 form: 256^3 (1,1,0) wave,
+    """The 256^3 benchmark workload in the FP32 form: (1,1,0) wave,
     A = 0.1, tau = 0.6.  Every z-plane equals the others bit for bit, and the
     fields stay within 1e-5 of the FP64 oracle (256 x 256 x 1, exact by the
     wave's plane symmetry) for the first steps; after that the FP32 floor of
