@@ -15,6 +15,7 @@ same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--form fp64|fp32]
                     [--path split|fused] [--collision bgk|regularized] [--no-cpu]
+    python bench.py --cpu-table   (the oracle alone: single-threaded and all host threads)
 """
 
 from __future__ import annotations
@@ -97,7 +98,68 @@ def cpu_baseline(n: int, tau: float, target_s: float = 15.0) -> dict:
     }
 
 
+CPU_CASES = {
+    # name: (description, nx, ny, nz, steps at all threads, steps single-threaded, workload)
+    "c1": ("1D x-wave, 100 sites, A=0.01, tau=0.6", 100, 1, 1, 1000, 1000, "x"),
+    "64cubed": ("3D x-wave 64^3, A=0.1, tau=0.6", 64, 64, 64, 20, 4, "x"),
+    "128cubed": ("3D x-wave 128^3, A=0.1, tau=0.6", 128, 128, 128, 10, 1, "x"),
+}
+
+
+def cpu_case(name: str, single: bool) -> dict:
+    """The oracle on one CPU case (run in a child process whose OpenMP
+    thread count is set by its environment)."""
+    import oracle
+    import workloads
+
+    desc, nx, ny, nz, steps_all, steps_one, _ = CPU_CASES[name]
+    steps = steps_one if single else steps_all
+    A = 0.01 if name == "c1" else 0.1
+    o = oracle.Oracle(nx, ny, nz, 0.6)
+    o.init_fields(workloads.gauge_wave_x(nx, ny, nz, A, float(nx)))
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    n = nx * ny * nz
+    return {"case": desc, "threads": oracle.num_threads(), "steps": steps, "seconds": dt,
+            "site_updates_per_s": n * steps / dt, "field_site_updates_per_s": FIELDS * n * steps / dt}
+
+
+def cpu_table() -> int:
+    """The oracle timed single-threaded and on all host threads (one child
+    process per measurement, OMP_NUM_THREADS set for it)."""
+    import subprocess
+
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    allt = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    rows = []
+    for name in CPU_CASES:
+        for threads in ("1", allt):
+            env = dict(os.environ, OMP_NUM_THREADS=threads)
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-case", name,
+                                "--single" if threads == "1" else "--all"],
+                               env=env, capture_output=True, text=True, check=True)
+            rows.append(json.loads(r.stdout.strip().splitlines()[-1]))
+            print(json.dumps(rows[-1]), flush=True)
+    print(json.dumps({"cpu_model": model, "logical_cpus": os.cpu_count(), "omp_all_threads": int(allt),
+                      "kind": "oracle", "rows": rows}), flush=True)
+    return 0
+
+
 def main() -> int:
+    if "--cpu-case" in sys.argv:
+        name = sys.argv[sys.argv.index("--cpu-case") + 1]
+        print(json.dumps(cpu_case(name, "--single" in sys.argv)), flush=True)
+        return 0
+    if "--cpu-table" in sys.argv:
+        return cpu_table()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)

@@ -34,3 +34,12 @@ def test_traffic_summary_is_used_only_for_matching_sources():
         assert abs(t / 256 ** 3 - d["bytes_per_site_per_step"]) < 1e-6
     else:
         assert t is None
+
+
+def test_cpu_case_runs_the_oracle_alone():
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--cpu-case", "c1", "--single"],
+                       capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stderr
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    assert d["threads"] == 1 and d["steps"] == 1000 and d["site_updates_per_s"] > 0
