@@ -80,7 +80,10 @@ extern "C" {
                                        same moments and first-order dynamics,
                                        no higher non-equilibrium moments (the
                                        paper suggests a stabilised collision
-                                       without specifying one); split path */
+                                       without specifying one).  It delays
+                                       the blow-up for tau <= 0.65 and ends
+                                       runs earlier for tau >= 1.5; split
+                                       path only */
 
 typedef struct lb_handle lb_handle; /* opaque, owned by the library */
 

@@ -519,3 +519,22 @@ def test_regularized_delays_the_grid_scale_blow_up():
         return 3000
     lb, lr = life(oracle.COLLISION_BGK), life(oracle.COLLISION_REGULARIZED)
     assert lb <= 200 and lr >= 4 * lb, (lb, lr)
+
+
+def test_regularized_is_a_small_tau_variant_only():
+    """The other side of the trade: at large tau the regularized collision
+    ends the gauge wave earlier than BGK (400 sites, A = 1e-3, tau = 2.0:
+    ~900 against ~1600 steps), so it is no replacement for the paper's BGK
+    at the paper's own relaxation times."""
+    def life(collision):
+        o = oracle.Oracle(400, 1, 1, 2.0, collision=collision)
+        o.init_fields(workloads.gauge_wave_x(400, 1, 1, 1e-3, 400.0))
+        for n in range(100, 4001, 100):
+            o.step(100)
+            u = o.moments()
+            ua = workloads.gauge_wave_x(400, 1, 1, 1e-3, 400.0, t=n)
+            if not np.all(np.isfinite(u)) or np.abs(u[1] - ua[1]).max() > 0.1 * np.abs(ua[1] - 1).max():
+                return n
+        return 4000
+    lb, lr = life(oracle.COLLISION_BGK), life(oracle.COLLISION_REGULARIZED)
+    assert lr < lb, (lb, lr)
