@@ -144,3 +144,29 @@ def test_matter_rejected_on_fused_path():
         with pytest.raises(lb.LBError):
             g.set_matter(np.zeros(10))
         g.set_matter(None)  # vacuum is always accepted
+
+
+def test_uniform_matter_changes_between_step_calls():
+    """Uniform matter travels in the launch arguments: a value changed
+    between step calls must reach the following steps, whichever buffer holds
+    the state (odd step counts in between)."""
+    _torch()
+    from paper_1505_02037_amd import lb
+
+    u0 = workloads.random_state(6, 5, 4, seed=81, amp=0.02)
+    o = oracle.Oracle(6, 5, 4, 0.9, oracle.GEODESIC)
+    with lb.Lattice(6, 5, 4, 0.9, slicing=lb.GEODESIC, device=0) as g:
+        for h in (o, g):
+            h.init_fields(u0)
+        for k, n in enumerate((64, 7, 32, 33, 96)):
+            G = np.full(10, 1e-4 * (k + 1))
+            o.set_matter(G)
+            g.set_matter(G)
+            o.step(n)
+            g.step(n)
+            _assert_equal(g.distributions(), o.distributions(), f"distributions after call {k}")
+        o.set_matter(None)
+        g.set_matter(None)
+        o.step(64)
+        g.step(64)
+        _assert_equal(g.moments(), o.moments(), "moments after returning to vacuum")
