@@ -25,9 +25,13 @@ FLAGS = [
 ]
 
 
+# roctx ranges around the library calls (visible in a profiler's marker trace)
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+
+
 def build(verbose: bool = False, extra=None) -> str:
     cmd = ["/opt/rocm/bin/hipcc", *FLAGS, *(extra or []),
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", LIB + ".tmp"]
+           *[os.path.join(CSRC, s) for s in SOURCES], *LIBS, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -11,6 +11,7 @@
 
 #include "../../include/lb.h"
 #include "lb_kernels.h"
+#include "lb_trace.h"
 
 using lbnr::Geom;
 
@@ -242,6 +243,7 @@ void lb_destroy(lb_handle *h)
 
 int lb_init_fields(lb_handle *h, const double *u0, int on_device)
 {
+    lbnr::TraceRange trace("lb_init_fields");
     if (!h || !u0) return LB_EINVAL;
     DeviceGuard dg(h->device);
     const Geom &G = h->G;
@@ -267,6 +269,7 @@ int lb_init_fields(lb_handle *h, const double *u0, int on_device)
 
 int lb_step(lb_handle *h, long long nsteps)
 {
+    lbnr::TraceRange trace("lb_step");
     if (!h || nsteps < 0) return LB_EINVAL;
     if (!h->initialised) return LB_ESTATE;
     if (nsteps == 0) return LB_OK;
@@ -330,6 +333,7 @@ int lb_step(lb_handle *h, long long nsteps)
 
 int lb_moments(lb_handle *h, double *u_out, int on_device)
 {
+    lbnr::TraceRange trace("lb_moments");
     if (!h || !u_out) return LB_EINVAL;
     if (!h->initialised) return LB_ESTATE;
     DeviceGuard dg(h->device);
@@ -346,6 +350,7 @@ int lb_moments(lb_handle *h, double *u_out, int on_device)
 
 int lb_get_distributions(lb_handle *h, double *f_out, int on_device)
 {
+    lbnr::TraceRange trace("lb_get_distributions");
     if (!h || !f_out) return LB_EINVAL;
     if (!h->initialised) return LB_ESTATE;
     DeviceGuard dg(h->device);
@@ -375,6 +380,7 @@ int lb_get_distributions(lb_handle *h, double *f_out, int on_device)
 
 int lb_error_norms(lb_handle *h, const double *u_ref, int on_device, double *max_abs, double *l2, double *ref_max)
 {
+    lbnr::TraceRange trace("lb_error_norms");
     if (!h || !u_ref) return LB_EINVAL;
     if (!h->initialised) return LB_ESTATE;
     DeviceGuard dg(h->device);

@@ -23,6 +23,7 @@
 #include "lb_kernels.h"
 #include "lb_site.h"
 #include "lb_step.h"
+#include "lb_trace.h"
 
 namespace lbnr {
 
@@ -474,6 +475,7 @@ int lb_server_submit(lb_server *s, const lb_config *cfg, const double *u0, long 
 
 int lb_server_advance(lb_server *s, int *active)
 {
+    lbnr::TraceRange trace("lb_server_advance");
     if (!s) return LB_EINVAL;
     DevGuard dg(s->device);
     int rc = admit(s);
