@@ -131,6 +131,21 @@ int lb_moments(lb_handle *h, double *u_out, int on_device);
  * Synchronises the handle's stream. */
 int lb_get_distributions(lb_handle *h, double *f_out, int on_device);
 
+/* Checkpoint/resume: replaces the state by the distributions f_in
+ * ([16][Q][nz][ny][nx], the layout lb_get_distributions writes), the exact
+ * inverse of lb_get_distributions in the FP64 form (resuming from a saved
+ * state continues bit for bit; saving only the fields u and calling
+ * lb_init_fields would drop the non-equilibrium part).  In the FP32-deviation
+ * form the values are rounded to FP32 deviations again.  Resets the step
+ * counter; the handle counts as initialised.  Synchronises the handle's
+ * stream, so f_in may be released on return. */
+int lb_set_distributions(lb_handle *h, const double *f_in, int on_device);
+
+/* Failure check: *all_finite = 1 if every moment of every site is finite,
+ * 0 if any is NaN or infinite (the scheme's blow-up); computed on the device
+ * (one moments pass and a reduction).  Synchronises the handle's stream. */
+int lb_check_finite(lb_handle *h, int *all_finite);
+
 /* Matter: the energy-momentum tensor G (units c = 8 pi G = 1, lattice units)
  * in the sources of the extrinsic-curvature and momentum-variable equations
  * (section "Bona-Masso evolution equations"; section "Expansion of flat

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbnr.so")
 PROBE_LIB = os.path.join(HERE, "libhbmprobe.so")
-SOURCES = ["lb_api.hip", "lb_fp64.hip", "lb_fp32.hip", "lb_fused.hip", "lb_serve.hip"]
+SOURCES = ["lb_api.hip", "lb_fp64.hip", "lb_fp32.hip", "lb_fused.hip", "lb_serve.hip", "lb_state.hip"]
 ARCH = os.environ.get("LBNR_ARCH", "gfx950")
 
 FLAGS = [

@@ -11,6 +11,7 @@
 
 #include "../../include/lb.h"
 #include "lb_kernels.h"
+#include "lb_state.h"
 #include "lb_trace.h"
 
 using lbnr::Geom;
@@ -375,6 +376,58 @@ int lb_get_distributions(lb_handle *h, double *f_out, int on_device)
         LB_HIP(hipMemcpyAsync(f_out, dst, (size_t)16 * G.nq * G.nsite * sizeof(double), hipMemcpyDeviceToHost,
                               h->stream));
     LB_HIP(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_set_distributions(lb_handle *h, const double *f_in, int on_device)
+{
+    lbnr::TraceRange trace("lb_set_distributions");
+    if (!h || !f_in) return LB_EINVAL;
+    DeviceGuard dg(h->device);
+    const Geom &G = h->G;
+    const size_t n = (size_t)G.nq * G.nsite; // doubles per field
+    if (fp32(h)) {
+        // one field at a time through the spare buffer (Q doubles per site)
+        for (int F = 0; F < 16; ++F) {
+            const double *src = f_in + (size_t)F * n;
+            if (!on_device) {
+                double *stage = spare(h);
+                LB_HIP(hipMemcpyAsync(stage, src, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+                src = stage;
+            }
+            LB_HIP(lbnr::launch_scatter32(src, G, F, (float *)h->fbuf[h->cur], h->stream));
+            if (!on_device) LB_HIP(hipStreamSynchronize(h->stream));
+        }
+    } else {
+        const double *src = f_in;
+        if (!on_device) {
+            double *stage = spare(h);
+            LB_HIP(hipMemcpyAsync(stage, f_in, 16 * n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+            src = stage;
+        }
+        LB_HIP(lbnr::launch_scatter(src, G, (double *)h->fbuf[h->cur], h->stream));
+    }
+    LB_HIP(hipStreamSynchronize(h->stream));
+    h->initialised = true;
+    h->ubar_valid = false;
+    h->steps = 0;
+    return LB_OK;
+}
+
+int lb_check_finite(lb_handle *h, int *all_finite)
+{
+    lbnr::TraceRange trace("lb_check_finite");
+    if (!h || !all_finite) return LB_EINVAL;
+    if (!h->initialised) return LB_ESTATE;
+    DeviceGuard dg(h->device);
+    int *scratch = (int *)spare(h);
+    LB_HIP(run_moments(h));
+    LB_HIP(lbnr::launch_finite(h->G, h->ubar, scratch, h->stream));
+    int bad = 1;
+    LB_HIP(hipMemcpyAsync(&bad, scratch + lbnr::finite_scratch_ints(h->G) - 1, sizeof(int), hipMemcpyDeviceToHost,
+                          h->stream));
+    LB_HIP(hipStreamSynchronize(h->stream));
+    *all_finite = bad ? 0 : 1;
     return LB_OK;
 }
 

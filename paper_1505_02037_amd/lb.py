@@ -45,7 +45,8 @@ NQ = 19
 EXPORTS = (
     "lb_create", "lb_device_bytes", "lb_init_fields", "lb_step", "lb_moments",
     "lb_get_distributions", "lb_error_norms", "lb_steps_done", "lb_set_timing",
-    "lb_kernel_times", "lb_set_matter", "lb_destroy", "lb_strerror", "lb_last_error",
+    "lb_kernel_times", "lb_set_matter", "lb_set_distributions", "lb_check_finite", "lb_destroy",
+    "lb_strerror", "lb_last_error",
 )
 
 
@@ -97,6 +98,8 @@ def load_library():
     lib.lb_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), dp, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int)]
     lib.lb_set_matter.argtypes = [P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int]
+    lib.lb_set_distributions.argtypes = [P, P, ctypes.c_int]
+    lib.lb_check_finite.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
     lib.lb_destroy.argtypes = [P]
     lib.lb_destroy.restype = None
     lib.lb_strerror.argtypes = [ctypes.c_int]
@@ -200,6 +203,17 @@ class Lattice:
         p, dev = _ptr(out, NF * self.nq * self.nsite)
         _check(self._lib.lb_get_distributions(self._h, p, dev), "lb_get_distributions")
         return out
+
+    def set_distributions(self, f) -> None:
+        """Restore a state saved with distributions() (checkpoint/resume)."""
+        p, dev = _ptr(f, NF * self.nq * self.nsite)
+        _check(self._lib.lb_set_distributions(self._h, p, dev), "lb_set_distributions")
+
+    def check_finite(self) -> bool:
+        """True if every moment of every site is finite."""
+        ok = ctypes.c_int()
+        _check(self._lib.lb_check_finite(self._h, ctypes.byref(ok)), "lb_check_finite")
+        return bool(ok.value)
 
     def set_matter(self, M, kind: int = MATTER_TENSOR) -> None:
         """Matter in lattice units (lb_set_matter): kind MATTER_TENSOR, M =

@@ -66,3 +66,67 @@ def test_device_bytes_fit_and_oversize_fails_cleanly():
     with lb.Lattice(8, 8, 8, 0.8, device=0) as g:
         g.init_fields(workloads.minkowski(8, 8, 8))
         g.step(1)
+
+
+@pytest.mark.parametrize("lattice,shape,collision,matter", [
+    (19, (5, 7, 13), 0, False),
+    (19, (4, 6, 9), 1, True),
+    (9, (1, 11, 17), 0, False),
+])
+def test_checkpoint_resume_is_exact(lattice, shape, collision, matter):
+    """Saving the distributions after 10 steps and resuming them in a new
+    handle continues bit for bit like the uninterrupted run (host and device
+    buffers)."""
+    lb = _lb()
+    import torch
+
+    nz, ny, nx = shape
+    u0 = workloads.random_state(nx, ny, nz, seed=91, amp=0.03)
+    G = workloads.random_matter(nx, ny, nz, seed=92, amp=1e-3) if matter else None
+    kw = dict(device=0, lattice=lattice, collision=collision)
+    with lb.Lattice(nx, ny, nz, 0.8, **kw) as a:
+        if matter:
+            a.set_matter(G)
+        a.init_fields(u0)
+        a.step(10)
+        saved = a.distributions()
+        a.step(15)
+        ua, fa = a.moments(), a.distributions()
+    for on_device in (False, True):
+        with lb.Lattice(nx, ny, nz, 0.8, **kw) as b:
+            if matter:
+                b.set_matter(G)
+            b.set_distributions(torch.from_numpy(saved).cuda() if on_device else saved)
+            assert b.steps_done == 0
+            b.step(15)
+            assert np.array_equal(b.moments(), ua) and np.array_equal(b.distributions(), fa)
+
+
+def test_checkpoint_resume_fp32():
+    lb = _lb()
+    u0 = workloads.random_state(13, 7, 5, seed=93, amp=0.03)
+    with lb.Lattice(13, 7, 5, 0.8, precision=lb.FP32_DEV, device=0) as a:
+        a.init_fields(u0)
+        a.step(10)
+        saved = a.distributions()
+        a.step(15)
+        ua = a.moments()
+    with lb.Lattice(13, 7, 5, 0.8, precision=lb.FP32_DEV, device=0) as b:
+        b.set_distributions(saved)
+        b.step(15)
+        ub = b.moments()
+    assert np.abs(ub - ua).max() <= 1e-12
+
+
+def test_check_finite_reports_the_blow_up():
+    """The 1D gauge wave at tau = 0.55 goes non-finite after ~120 steps (the
+    scheme's grid-scale instability); the check reports it, the run before it
+    is finite."""
+    lb = _lb()
+    with lb.Lattice(100, 1, 1, 0.55, device=0) as g:
+        g.init_fields(workloads.gauge_wave_x(100, 1, 1, 0.01, 100.0))
+        g.step(50)
+        assert g.check_finite()
+        g.step(350)
+        assert not g.check_finite()
+        assert not np.all(np.isfinite(g.moments()))
