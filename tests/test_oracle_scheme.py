@@ -538,3 +538,22 @@ def test_regularized_is_a_small_tau_variant_only():
         return 4000
     lb, lr = life(oracle.COLLISION_BGK), life(oracle.COLLISION_REGULARIZED)
     assert lr < lb, (lb, lr)
+
+
+@pytest.mark.parametrize("slicing", [oracle.HARMONIC, oracle.GEODESIC, oracle.ONE_PLUS_LOG])
+def test_lapse_stage_matches_the_pinned_point_equation(slicing):
+    """On one site (no streaming, no derivatives) one step adds exactly R to
+    each field's distribution sum, and the lapse's R is computed by the time
+    step's own lapse/metric stage.  It must equal the right-hand side of the
+    point routine (pinned by the exact and manufactured solutions, the
+    "1+log" one included) at the raw moments."""
+    o = oracle.Oracle(1, 1, 1, 0.8, slicing)
+    o.init_fields(workloads.random_state(1, 1, 1, seed=17, amp=0.05))
+    o.step(2)
+    ub = o.distributions().sum(axis=1)[:, 0, 0, 0]
+    o.step(1)
+    gain = o.distributions()[0].sum() - ub[0]
+    r = oracle.point_rhs(ub[0], ub[1:7], ub[7:13], ub[13:16], np.zeros(3), np.zeros(18), slicing)
+    assert abs(gain - r["R_alpha"]) <= 1e-16 + 1e-13 * abs(r["R_alpha"])
+    if slicing != oracle.GEODESIC:
+        assert abs(r["R_alpha"]) > 1e-4
