@@ -198,7 +198,8 @@ void lb_destroy(lb_handle *h);
 
 /* Static text naming an LB_* code. */
 const char *lb_strerror(int code);
-/* Text of the last HIP failure seen by this thread (empty if none). */
+/* Text of the last HIP failure seen by this thread in any lb_* or lb_server_*
+ * call (empty if none; a later successful call does not clear it). */
 const char *lb_last_error(void);
 
 #ifdef __cplusplus

@@ -17,8 +17,10 @@
  * run join them as memory and slots free up.
  *
  * Conventions as in include/lb.h (u arrays are host double [16][nz][ny][nx]).
- * Every int-returning function returns LB_OK or a negative LB_E* code.  One
- * server is driven from one host thread at a time.
+ * Every int-returning function returns LB_OK or a negative LB_E* code; after
+ * LB_EDEVICE, lb_last_error() names the failed HIP call.  A device that cannot
+ * be made current is LB_EDEVICE.  One server is driven from one host thread at
+ * a time.
  */
 #ifndef LBNR_LB_SERVE_H
 #define LBNR_LB_SERVE_H

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -10,6 +11,7 @@
 #include <vector>
 
 #include "../../include/lb.h"
+#include "lb_error.h"
 #include "lb_kernels.h"
 #include "lb_state.h"
 #include "lb_trace.h"
@@ -25,12 +27,22 @@ static_assert(LB_COLLISION_BGK == lbnr::kCollisionBgk && LB_COLLISION_REGULARIZE
               "collision kinds of the C-ABI and the kernels");
 
 namespace {
-
 thread_local char g_last_error[256] = "";
+} // namespace
+
+void lbnr::set_last_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+}
+
+namespace {
 
 int fail_hip(hipError_t e, const char *what)
 {
-    snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
+    lbnr::set_last_error("%s: %s", what, hipGetErrorString(e));
     return LB_EDEVICE;
 }
 
@@ -48,12 +60,19 @@ struct DeviceGuard {
     {
         if (hipGetDevice(&prev) != hipSuccess) return;
         ok = (dev < 0 || dev == prev) || hipSetDevice(dev) == hipSuccess;
+        if (!ok) (void)hipGetLastError(); // the refusal is reported by the caller, not by a later launch check
     }
     ~DeviceGuard()
     {
         if (prev >= 0) (void)hipSetDevice(prev);
     }
 };
+
+// Makes the handle's device current for the scope of a call (an error if it
+// cannot be made current).
+#define LB_ON_DEVICE(h)                                                  \
+    DeviceGuard dg_(h->device);                                          \
+    if (!dg_.ok) return fail_hip(hipErrorInvalidDevice, "hipSetDevice")
 
 size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
 
@@ -236,7 +255,7 @@ int lb_create(const lb_config *cfg, lb_handle **out)
 void lb_destroy(lb_handle *h)
 {
     if (!h) return;
-    DeviceGuard dg(h->device);
+    DeviceGuard dg(h->device); // best effort: the memory is released either way
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     free_all(h);
     delete h;
@@ -246,7 +265,7 @@ int lb_init_fields(lb_handle *h, const double *u0, int on_device)
 {
     lbnr::TraceRange trace("lb_init_fields");
     if (!h || !u0) return LB_EINVAL;
-    DeviceGuard dg(h->device);
+    LB_ON_DEVICE(h);
     const Geom &G = h->G;
     const size_t ubytes = (size_t)16 * G.nsite * sizeof(double);
     const double *du0 = u0;
@@ -274,7 +293,7 @@ int lb_step(lb_handle *h, long long nsteps)
     if (!h || nsteps < 0) return LB_EINVAL;
     if (!h->initialised) return LB_ESTATE;
     if (nsteps == 0) return LB_OK;
-    DeviceGuard dg(h->device);
+    LB_ON_DEVICE(h);
     const int slicing = h->cfg.slicing;
     if (h->fused && !h->ubar_valid) {
         // the fused step starts from the current state's moments
@@ -337,7 +356,7 @@ int lb_moments(lb_handle *h, double *u_out, int on_device)
     lbnr::TraceRange trace("lb_moments");
     if (!h || !u_out) return LB_EINVAL;
     if (!h->initialised) return LB_ESTATE;
-    DeviceGuard dg(h->device);
+    LB_ON_DEVICE(h);
     const Geom &G = h->G;
     const int slicing = h->cfg.slicing;
     double *dst = on_device ? u_out : spare(h);
@@ -354,7 +373,7 @@ int lb_get_distributions(lb_handle *h, double *f_out, int on_device)
     lbnr::TraceRange trace("lb_get_distributions");
     if (!h || !f_out) return LB_EINVAL;
     if (!h->initialised) return LB_ESTATE;
-    DeviceGuard dg(h->device);
+    LB_ON_DEVICE(h);
     const Geom &G = h->G;
     if (fp32(h)) {
         // one field at a time: the spare buffer holds Q doubles per site
@@ -383,7 +402,7 @@ int lb_set_distributions(lb_handle *h, const double *f_in, int on_device)
 {
     lbnr::TraceRange trace("lb_set_distributions");
     if (!h || !f_in) return LB_EINVAL;
-    DeviceGuard dg(h->device);
+    LB_ON_DEVICE(h);
     const Geom &G = h->G;
     const size_t n = (size_t)G.nq * G.nsite; // doubles per field
     if (fp32(h)) {
@@ -419,7 +438,7 @@ int lb_check_finite(lb_handle *h, int *all_finite)
     lbnr::TraceRange trace("lb_check_finite");
     if (!h || !all_finite) return LB_EINVAL;
     if (!h->initialised) return LB_ESTATE;
-    DeviceGuard dg(h->device);
+    LB_ON_DEVICE(h);
     int *scratch = (int *)spare(h);
     LB_HIP(run_moments(h));
     LB_HIP(lbnr::launch_finite(h->G, h->ubar, scratch, h->stream));
@@ -436,7 +455,7 @@ int lb_error_norms(lb_handle *h, const double *u_ref, int on_device, double *max
     lbnr::TraceRange trace("lb_error_norms");
     if (!h || !u_ref) return LB_EINVAL;
     if (!h->initialised) return LB_ESTATE;
-    DeviceGuard dg(h->device);
+    LB_ON_DEVICE(h);
     const Geom &G = h->G;
     const int slicing = h->cfg.slicing;
     // spare buffer layout: [u 16 x nsite][ref 16 x nsite][norm scratch]
@@ -473,7 +492,7 @@ int lb_set_matter(lb_handle *h, int kind, const double *M, int per_site, int on_
         return LB_OK;
     }
     if (h->fused) return LB_EINVAL; // the z-marching launch evaluates vacuum sources only
-    DeviceGuard dg(h->device);
+    LB_ON_DEVICE(h);
     const int nc = kind == LB_MATTER_FLUID ? 2 : 10;
     const Geom &G = h->G;
     if (!per_site) {

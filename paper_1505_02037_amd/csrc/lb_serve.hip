@@ -20,6 +20,7 @@
 
 #include "../../include/lb.h"
 #include "../../include/lb_serve.h"
+#include "lb_error.h"
 #include "lb_kernels.h"
 #include "lb_site.h"
 #include "lb_step.h"
@@ -96,8 +97,6 @@ using lbnr::WorkItem;
 
 namespace {
 
-thread_local char g_err[256] = "";
-
 double now_s()
 {
     using namespace std::chrono;
@@ -106,8 +105,8 @@ double now_s()
 
 int hip_fail(hipError_t e, const char *what)
 {
-    snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
-    fprintf(stderr, "lb_serve: %s\n", g_err);
+    lbnr::set_last_error("%s: %s", what, hipGetErrorString(e));
+    fprintf(stderr, "lb_serve: %s: %s\n", what, hipGetErrorString(e));
     return LB_EDEVICE;
 }
 
@@ -117,11 +116,16 @@ int hip_fail(hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(e_, #call);     \
     } while (0)
 
+// Keeps the caller's current device and restores it on scope exit; `ok` tells
+// whether the requested device could be made current.
 struct DevGuard {
     int prev = -1;
+    bool ok = false;
     explicit DevGuard(int dev)
     {
-        if (hipGetDevice(&prev) == hipSuccess && dev >= 0 && dev != prev) (void)hipSetDevice(dev);
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = (dev < 0 || dev == prev) || hipSetDevice(dev) == hipSuccess;
+        if (!ok) (void)hipGetLastError(); // the refusal is reported by the caller, not by a later launch check
     }
     ~DevGuard()
     {
@@ -417,6 +421,7 @@ int lb_server_create(const lb_server_config *cfg, lb_server **out)
         return LB_EINVAL;
     if (cfg->precision != LB_FP64 && cfg->precision != LB_FP32_DEV) return LB_EINVAL;
     DevGuard dg(cfg->device);
+    if (!dg.ok) return hip_fail(hipErrorInvalidDevice, "hipSetDevice");
     lb_server *s = new (std::nothrow) lb_server();
     if (!s) return LB_ENOMEM;
     s->cfg = *cfg;
@@ -441,7 +446,7 @@ int lb_server_create(const lb_server_config *cfg, lb_server **out)
         if (s->arena_base) (void)hipFree(s->arena_base);
         if (s->ddesc) (void)hipFree(s->ddesc);
         delete s;
-        snprintf(g_err, sizeof g_err, "lb_server_create: %s", hipGetErrorString(e));
+        lbnr::set_last_error("lb_server_create: %s", hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE;
     }
     s->arena.reset(s->cfg.hbm_budget_bytes);
@@ -478,6 +483,7 @@ int lb_server_advance(lb_server *s, int *active)
     lbnr::TraceRange trace("lb_server_advance");
     if (!s) return LB_EINVAL;
     DevGuard dg(s->device);
+    if (!dg.ok) return hip_fail(hipErrorInvalidDevice, "hipSetDevice");
     int rc = admit(s);
     if (rc != LB_OK) return rc;
     if (s->dirty) {
@@ -545,7 +551,7 @@ int lb_server_get_stats(const lb_server *s, lb_server_stats *st)
 void lb_server_destroy(lb_server *s)
 {
     if (!s) return;
-    DevGuard dg(s->device);
+    DevGuard dg(s->device); // best effort: the memory is released either way
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     if (s->exec) (void)hipGraphExecDestroy(s->exec);
     if (s->ditems) (void)hipFree(s->ditems);

@@ -48,7 +48,7 @@ def test_bad_device_is_an_error_not_a_fault():
     lb = _lb()
     import torch
 
-    with pytest.raises(lb.LBError):
+    with pytest.raises(lb.LBError, match="hipSetDevice"):
         lb.Lattice(8, 8, 8, 0.8, device=torch.cuda.device_count() + 3)
 
 

@@ -111,6 +111,17 @@ def test_nonfinite_request_is_failed_and_isolated():
         assert not np.isfinite(srv.result(ib)).all()
 
 
+def test_bad_device_is_an_error_not_a_fault():
+    _need_gpu()
+    import torch
+    from paper_1505_02037_amd import lb, serve
+
+    with pytest.raises(lb.LBError, match="hipSetDevice"):
+        serve.Server(1 << 20, lb.FP64, device=torch.cuda.device_count() + 3)
+    with serve.Server(1 << 20, lb.FP64, device=0) as srv:  # still usable afterwards
+        assert srv.stats()["resident"] == 0
+
+
 def test_trace_driver_reports_tts():
     _need_gpu()
     from paper_1505_02037_amd import lb, serve
