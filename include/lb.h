@@ -181,7 +181,7 @@ long long lb_steps_done(const lb_handle *h);
 
 /* Enables (1) or disables (0) HIP-event timing of the step kernels.  A timed
  * lb_step records an event around every launch and synchronises the stream
- * at its end. */
+ * after every 256 steps and at its end. */
 int lb_set_timing(lb_handle *h, int enable);
 
 /* Average device time in milliseconds of each kernel of the last lb_step

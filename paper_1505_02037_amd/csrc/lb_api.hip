@@ -234,7 +234,7 @@ int lb_create(const lb_config *cfg, lb_handle **out)
         (void)hipGetLastError();
         free_all(h);
         delete h;
-        snprintf(g_last_error, sizeof g_last_error, "hipMalloc: %s", hipGetErrorString(e));
+        lbnr::set_last_error("hipMalloc: %s", hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE;
     }
     if (cfg->stream) {
@@ -301,47 +301,56 @@ int lb_step(lb_handle *h, long long nsteps)
         h->ubar_valid = true;
     }
     const int per_step = h->fused ? 1 : 2;
-    if (h->timing) {
-        int rc = ensure_events(h, (size_t)per_step * nsteps + 1);
-        if (rc != LB_OK) return rc;
-        LB_HIP(hipEventRecord(h->events[0], h->stream));
-    }
-    for (long long s = 0; s < nsteps; ++s) {
-        if (h->fused) {
-            if (fp32(h))
-                LB_HIP(lbnr::launch_fused32((const float *)h->fbuf[h->cur], (float *)h->fbuf[h->cur ^ 1], h->G,
-                                            slicing, h->omega, h->srcfac, h->ubar, h->ubar2, h->stream));
-            else
-                LB_HIP(lbnr::launch_fused64((const double *)h->fbuf[h->cur], (double *)h->fbuf[h->cur ^ 1], h->G,
-                                            slicing, h->omega, h->srcfac, h->ubar, h->ubar2, h->stream));
-            double *t = h->ubar;
-            h->ubar = h->ubar2;
-            h->ubar2 = t;
-            if (h->timing) LB_HIP(hipEventRecord(h->events[s + 1], h->stream));
-        } else {
-            LB_HIP(run_moments(h));
-            if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 1], h->stream));
-            LB_HIP(run_collide(h));
-            if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 2], h->stream));
-            h->ubar_valid = false;
+    // a timed call runs in chunks of at most kTimedChunk steps, each bracketed
+    // by its own events and synchronised, so the event count stays bounded
+    constexpr long long kTimedChunk = 256;
+    double tm = 0.0, tc = 0.0;
+    for (long long done = 0; done < nsteps;) {
+        const long long n = h->timing && nsteps - done > kTimedChunk ? kTimedChunk : nsteps - done;
+        if (h->timing) {
+            int rc = ensure_events(h, (size_t)per_step * n + 1);
+            if (rc != LB_OK) return rc;
+            LB_HIP(hipEventRecord(h->events[0], h->stream));
         }
-        h->cur ^= 1;
-        h->steps++;
-    }
-    if (h->timing) {
-        LB_HIP(hipStreamSynchronize(h->stream));
-        double tm = 0.0, tc = 0.0;
-        for (long long s = 0; s < nsteps; ++s) {
-            float a = 0.f, b = 0.f;
+        for (long long s = 0; s < n; ++s) {
             if (h->fused) {
-                LB_HIP(hipEventElapsedTime(&a, h->events[s], h->events[s + 1]));
+                if (fp32(h))
+                    LB_HIP(lbnr::launch_fused32((const float *)h->fbuf[h->cur], (float *)h->fbuf[h->cur ^ 1], h->G,
+                                                slicing, h->omega, h->srcfac, h->ubar, h->ubar2, h->stream));
+                else
+                    LB_HIP(lbnr::launch_fused64((const double *)h->fbuf[h->cur], (double *)h->fbuf[h->cur ^ 1],
+                                                h->G, slicing, h->omega, h->srcfac, h->ubar, h->ubar2, h->stream));
+                double *t = h->ubar;
+                h->ubar = h->ubar2;
+                h->ubar2 = t;
+                if (h->timing) LB_HIP(hipEventRecord(h->events[s + 1], h->stream));
             } else {
-                LB_HIP(hipEventElapsedTime(&a, h->events[2 * s], h->events[2 * s + 1]));
-                LB_HIP(hipEventElapsedTime(&b, h->events[2 * s + 1], h->events[2 * s + 2]));
+                LB_HIP(run_moments(h));
+                if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 1], h->stream));
+                LB_HIP(run_collide(h));
+                if (h->timing) LB_HIP(hipEventRecord(h->events[2 * s + 2], h->stream));
+                h->ubar_valid = false;
             }
-            tm += a;
-            tc += b;
+            h->cur ^= 1;
+            h->steps++;
         }
+        if (h->timing) {
+            LB_HIP(hipStreamSynchronize(h->stream));
+            for (long long s = 0; s < n; ++s) {
+                float a = 0.f, b = 0.f;
+                if (h->fused) {
+                    LB_HIP(hipEventElapsedTime(&a, h->events[s], h->events[s + 1]));
+                } else {
+                    LB_HIP(hipEventElapsedTime(&a, h->events[2 * s], h->events[2 * s + 1]));
+                    LB_HIP(hipEventElapsedTime(&b, h->events[2 * s + 1], h->events[2 * s + 2]));
+                }
+                tm += a;
+                tc += b;
+            }
+        }
+        done += n;
+    }
+    if (h->timing) {
         h->ms_moments = tm / (double)nsteps;
         h->ms_collide = tc / (double)nsteps;
         h->timed_launches = nsteps;
@@ -513,7 +522,7 @@ int lb_set_matter(lb_handle *h, int kind, const double *M, int per_site, int on_
         hipError_t e = hipMalloc((void **)&h->matter_buf, (size_t)10 * G.ps * sizeof(double));
         if (e != hipSuccess) {
             h->matter_buf = nullptr;
-            snprintf(g_last_error, sizeof g_last_error, "hipMalloc: %s", hipGetErrorString(e));
+            lbnr::set_last_error("hipMalloc: %s", hipGetErrorString(e));
             (void)hipGetLastError();
             return e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE;
         }

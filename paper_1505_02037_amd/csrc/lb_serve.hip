@@ -274,9 +274,14 @@ int rebuild(lb_server *s)
     s->nitems = (int)items.size();
     if (nres) SV_HIP(hipMemcpyAsync(s->ddesc, s->hdesc.data(), nres * sizeof(ReqDesc), hipMemcpyHostToDevice, s->stream));
     if (items.size() > s->items_cap) {
-        if (s->ditems) SV_HIP(hipFree(s->ditems));
+        // the old list is dropped before the new one is allocated, so that a
+        // failed allocation leaves no stale pointer for lb_server_destroy
+        WorkItem *old = s->ditems;
+        s->ditems = nullptr;
+        s->items_cap = 0;
+        if (old) SV_HIP(hipFree(old));
+        SV_HIP(hipMalloc((void **)&s->ditems, items.size() * 2 * sizeof(WorkItem)));
         s->items_cap = items.size() * 2;
-        SV_HIP(hipMalloc((void **)&s->ditems, s->items_cap * sizeof(WorkItem)));
     }
     if (!items.empty())
         SV_HIP(hipMemcpyAsync(s->ditems, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,

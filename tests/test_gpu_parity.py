@@ -308,6 +308,27 @@ def test_kernel_timing_names_the_launched_kernels():
         assert all(v > 0 for v in t.values())
 
 
+def test_timed_steps_span_chunks_and_change_nothing():
+    """A timed call longer than one timing chunk (256 steps) gives the untimed
+    call's state bit for bit, and per-launch times averaged over all steps."""
+    _torch()
+    from paper_1505_02037_amd import lb
+
+    u0 = workloads.gauge_wave_x(12, 6, 5, 0.05, 12)
+    res = []
+    for path, timed in ((1, False), (1, True), (2, True)):
+        with lb.Lattice(12, 6, 5, 1.0, device=0, path=path) as g:
+            g.init_fields(u0)
+            g.set_timing(timed)
+            g.step(600)
+            if timed:
+                t = g.kernel_times()
+                assert len(t) == (2 if path == 1 else 1) and all(v > 0 for v in t.values())
+            res.append(g.distributions())
+    assert np.array_equal(res[0], res[1], equal_nan=True)
+    assert np.array_equal(res[0], res[2], equal_nan=True)
+
+
 def test_fused_and_split_paths_agree_after_moments_calls():
     """Interleaving output calls (which recompute the moments) with fused steps
     leaves the evolution unchanged."""
