@@ -126,6 +126,38 @@ def test_fp32_diagonal_256_cubed():
             assert max(err[0], err[1:7].max(), err[13:16].max()) <= 1e-7, (total, err)
 
 
+def test_fp32_random_state_256_cubed_sampled_sites():
+    """The FP32 form at the benchmark's lattice size with a random state:
+    after two steps the moments at sampled sites (corners, faces, random
+    sites) are within the FP32 bound of the FP64 oracle evolved on a window
+    around each site, and so are the distributions (a tenth of it)."""
+    torch = _torch()
+    import oracle_windows as ow
+
+    n, steps, tau = 256, 2, 0.6
+    print(f"[fp32] random state {n}^3, sampled sites after {steps} steps", flush=True)
+    u0 = workloads.random_state(n, n, n, seed=258, amp=0.05)
+    cs = ow.sample_centres(n, 18, seed=259)
+    uo, fo = ow.sampled(u0, cs, tau, steps)
+    iz, iy, ix = (torch.tensor([c[k] for c in cs], device="cuda") for k in range(3))
+    with _fp32((n, n, n), tau) as g:
+        g.init_fields(u0)
+        del u0
+        g.step(steps)
+        ug = torch.empty((16, n, n, n), dtype=torch.float64, device="cuda")
+        g.moments(ug)
+        us = ug[:, iz, iy, ix].cpu().numpy()
+        del ug
+        fg = torch.empty((16, 19, n, n, n), dtype=torch.float64, device="cuda")
+        g.distributions(fg)
+        fs = fg[:, :, iz, iy, ix].cpu().numpy()
+        del fg
+    torch.cuda.empty_cache()
+    err = _rel_err(us, uo)
+    assert err.max() <= TOL, err
+    assert np.abs(fs - fo).max() <= TOL * 0.1
+
+
 def test_fp32_fused_equals_split_bitwise():
     """The FP32 form's one-launch and two-launch steps run the same arithmetic."""
     _torch()

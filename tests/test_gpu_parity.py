@@ -244,6 +244,41 @@ def test_diagonal_wave_256_cubed_plane_by_plane():
         assert np.allclose(norms["l2"], l2, rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("path", list(PATHS))
+def test_random_state_256_cubed_sampled_sites(path):
+    """The benchmark's lattice size and launch configuration with a random,
+    not plane-symmetric, state: after two steps the moments and distributions
+    at sampled sites (corners and faces, where the periodic wrap acts, and
+    random sites) equal the oracle's bit for bit, the oracle evolving a
+    periodic window around each site (exact by locality, pinned in
+    tests/test_oracle_windows.py)."""
+    torch = _torch()
+    import oracle_windows as ow
+    from paper_1505_02037_amd import lb
+
+    n, steps, tau = 256, 2, 0.6
+    _say(f"[parity] random state {n}^3 path={path}, sampled sites after {steps} steps")
+    u0 = workloads.random_state(n, n, n, seed=256, amp=0.05)
+    cs = ow.sample_centres(n, 18, seed=257)
+    uo, fo = ow.sampled(u0, cs, tau, steps)
+    iz, iy, ix = (torch.tensor([c[k] for c in cs], device="cuda") for k in range(3))
+    with lb.Lattice(n, n, n, tau, device=0, path=PATHS[path]) as g:
+        g.init_fields(u0)
+        del u0
+        g.step(steps)
+        ug = torch.empty((16, n, n, n), dtype=torch.float64, device="cuda")
+        g.moments(ug)
+        us = ug[:, iz, iy, ix].cpu().numpy()
+        del ug
+        fg = torch.empty((16, 19, n, n, n), dtype=torch.float64, device="cuda")
+        g.distributions(fg)
+        fs = fg[:, :, iz, iy, ix].cpu().numpy()
+        del fg
+    torch.cuda.empty_cache()
+    _assert_equal(us, uo, "moments at sampled sites")
+    _assert_equal(fs, fo, "distributions at sampled sites")
+
+
 def test_error_norms_small():
     torch = _torch()
     _say("[parity] error norms 9x8x7")
