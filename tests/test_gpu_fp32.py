@@ -187,14 +187,12 @@ def test_fp32_error_norms_and_kernel_names():
     assert np.array_equal(nr["max_abs"], np.abs(u - ref).reshape(16, -1).max(axis=1))
 
 
-def test_largest_fp32_lattice_rows_match_oracle():
-    """The largest configuration's launch shape: an FP32-deviation lattice
-    sized to fill the card (edge up to 488), x-wave A = 0.05, tau = 0.6.
-    After two steps every (y, z) row is identical (bitwise) and equals the
-    oracle's one-dimensional FP64 run within the FP32 bound."""
-    torch = _torch()
+def _largest_edge(torch):
+    """Edge (256..488, step 8) of the largest cubic FP32 lattice that fits the
+    free device memory beside one 16-field FP64 moments array and a margin."""
     from paper_1505_02037_amd import lb
 
+    torch.cuda.empty_cache()  # memory torch cached for earlier tests counts as free here
     free, _ = torch.cuda.mem_get_info()
     e = 256
     while e < 488:
@@ -203,6 +201,18 @@ def test_largest_fp32_lattice_rows_match_oracle():
         if need > free:
             break
         e = nxt
+    return e
+
+
+def test_largest_fp32_lattice_rows_match_oracle():
+    """The largest configuration's launch shape: an FP32-deviation lattice
+    sized to fill the card (edge up to 488), x-wave A = 0.05, tau = 0.6.
+    After two steps every (y, z) row is identical (bitwise) and equals the
+    oracle's one-dimensional FP64 run within the FP32 bound."""
+    torch = _torch()
+    from paper_1505_02037_amd import lb
+
+    e = _largest_edge(torch)
     print(f"[fp32] largest lattice {e}^3 ({e ** 3 / 1e6:.0f} M sites)", flush=True)
     A, tau, steps = 0.05, 0.6, 2
     row = torch.from_numpy(workloads.gauge_wave_x(e, 1, 1, A, float(e)))
@@ -218,4 +228,33 @@ def test_largest_fp32_lattice_rows_match_oracle():
     o.step(steps)
     err = _rel_err(u[:, :1, :1, :].cpu().numpy(), o.moments())
     del u
+    assert err.max() <= TOL, err
+
+
+def test_largest_fp32_lattice_random_state_sampled_sites():
+    """The largest lattice with a random, not plane-symmetric, state (64-bit
+    offsets of every field and direction in use): after two steps the moments
+    at sampled sites are within the FP32 bound of the FP64 oracle evolved on a
+    window around each site."""
+    torch = _torch()
+    import oracle_windows as ow
+    from paper_1505_02037_amd import lb
+
+    e = _largest_edge(torch)
+    steps, tau = 2, 0.6
+    print(f"[fp32] largest lattice {e}^3, random state, sampled sites after {steps} steps", flush=True)
+    u0 = workloads.random_state(e, e, e, seed=488, amp=0.05)
+    cs = ow.sample_centres(e, 18, seed=489)
+    uo, _ = ow.sampled(u0, cs, tau, steps)
+    iz, iy, ix = (torch.tensor([c[k] for c in cs], device="cuda") for k in range(3))
+    with lb.Lattice(e, e, e, tau, precision=lb.FP32_DEV, device=0) as g:
+        g.init_fields(u0)
+        del u0
+        g.step(steps)
+        u = torch.empty((16, e, e, e), dtype=torch.float64, device="cuda")
+        g.moments(u)
+        us = u[:, iz, iy, ix].cpu().numpy()
+        del u
+    torch.cuda.empty_cache()
+    err = _rel_err(us, uo)
     assert err.max() <= TOL, err
