@@ -244,8 +244,11 @@ def test_diagonal_wave_256_cubed_plane_by_plane():
         assert np.allclose(norms["l2"], l2, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("path", list(PATHS))
-def test_random_state_256_cubed_sampled_sites(path):
+@pytest.mark.parametrize("path,collision,slicing", [
+    ("split", 0, oracle.HARMONIC), ("fused", 0, oracle.HARMONIC),
+    ("split", 1, oracle.HARMONIC), ("split", 0, oracle.ONE_PLUS_LOG),
+], ids=["split", "fused", "split-regularized", "split-1pluslog"])
+def test_random_state_256_cubed_sampled_sites(path, collision, slicing):
     """The benchmark's lattice size and launch configuration with a random,
     not plane-symmetric, state: after two steps the moments and distributions
     at sampled sites (corners and faces, where the periodic wrap acts, and
@@ -257,12 +260,13 @@ def test_random_state_256_cubed_sampled_sites(path):
     from paper_1505_02037_amd import lb
 
     n, steps, tau = 256, 2, 0.6
-    _say(f"[parity] random state {n}^3 path={path}, sampled sites after {steps} steps")
+    _say(f"[parity] random state {n}^3 path={path} collision={collision} slicing={slicing}, "
+         f"sampled sites after {steps} steps")
     u0 = workloads.random_state(n, n, n, seed=256, amp=0.05)
     cs = ow.sample_centres(n, 18, seed=257)
-    uo, fo = ow.sampled(u0, cs, tau, steps)
+    uo, fo = ow.sampled(u0, cs, tau, steps, slicing=slicing, collision=collision)
     iz, iy, ix = (torch.tensor([c[k] for c in cs], device="cuda") for k in range(3))
-    with lb.Lattice(n, n, n, tau, device=0, path=PATHS[path]) as g:
+    with lb.Lattice(n, n, n, tau, slicing=slicing, device=0, path=PATHS[path], collision=collision) as g:
         g.init_fields(u0)
         del u0
         g.step(steps)
