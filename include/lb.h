@@ -87,6 +87,17 @@ extern "C" {
 
 typedef struct lb_handle lb_handle; /* opaque, owned by the library */
 
+/* Optional device allocator for the memory a handle holds (distribution
+ * buffers, per-site scratch, per-site matter): dev_alloc(bytes, ctx) returns
+ * `bytes` of device memory on the handle's device (the device is current
+ * during the call), aligned to at least 256 bytes, or NULL if it has none;
+ * dev_free(ptr, ctx) gives back what dev_alloc returned.  The library calls
+ * dev_free only after the handle's stream has finished with the memory.
+ * Lets a caller serve the library from its own pool (for example a
+ * framework's caching allocator). */
+typedef void *(*lb_dev_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*lb_dev_free_fn)(void *ptr, void *ctx);
+
 typedef struct lb_config {
     int lattice;     /* LB_D3Q19 or LB_D2Q9 */
     int nx, ny, nz;  /* periodic extents, each >= 1 */
@@ -100,11 +111,16 @@ typedef struct lb_config {
     int path;        /* LB_PATH_AUTO, LB_PATH_SPLIT or LB_PATH_FUSED: how a
                         step is launched; every path gives identical results */
     int collision;   /* LB_COLLISION_BGK (0) or LB_COLLISION_REGULARIZED */
+    lb_dev_alloc_fn dev_alloc; /* NULL: the library uses hipMalloc/hipFree */
+    lb_dev_free_fn dev_free;   /* required with dev_alloc */
+    void *alloc_ctx;           /* passed to dev_alloc and dev_free */
 } lb_config;
 
-/* Allocates two distribution buffers and per-site scratch on the device.
- * Fails with LB_EINVAL on a bad config, LB_ENOMEM if the device memory is
- * not available.  *out is set to NULL on failure. */
+/* Allocates two distribution buffers and per-site scratch on the device
+ * (through cfg->dev_alloc if set).  Fails with LB_EINVAL on a bad config
+ * (dev_alloc without dev_free included), LB_ENOMEM if the device memory is
+ * not available (or dev_alloc returns NULL).  *out is set to NULL on
+ * failure, with everything allocated so far given back. */
 int lb_create(const lb_config *cfg, lb_handle **out);
 
 /* Device bytes lb_create would allocate for cfg (0 on a bad config). */

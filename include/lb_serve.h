@@ -78,7 +78,8 @@ size_t lb_server_request_bytes(const lb_server *s, const lb_config *cfg);
 
 /* Queues an evolution of nsteps >= 0 steps from u0 (host, copied).  cfg's
  * lattice (LB_D3Q19 only), extents, tau and slicing are used; its precision,
- * device and stream are ignored (the server's apply).  LB_EINVAL if cfg is
+ * device, stream and allocator are ignored (the server's apply; requests
+ * live in the server's arena).  LB_EINVAL if cfg is
  * invalid, names another lattice, or the request can never fit the arena.
  * *id receives the request id. */
 int lb_server_submit(lb_server *s, const lb_config *cfg, const double *u0, long long nsteps,

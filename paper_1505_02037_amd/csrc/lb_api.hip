@@ -107,9 +107,36 @@ struct lb_handle {
 
 namespace {
 
+// device memory of a handle: the caller's allocator if the config names one
+hipError_t dev_malloc(lb_handle *h, void **p, size_t bytes)
+{
+    if (h->cfg.dev_alloc) {
+        *p = h->cfg.dev_alloc(bytes, h->cfg.alloc_ctx);
+        if (!*p) lbnr::set_last_error("dev_alloc returned NULL for %zu bytes", bytes);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        lbnr::set_last_error("hipMalloc: %s", hipGetErrorString(e));
+        (void)hipGetLastError();
+    }
+    return e;
+}
+
+void dev_release(lb_handle *h, void *p)
+{
+    if (!p) return;
+    if (h->cfg.dev_free)
+        h->cfg.dev_free(p, h->cfg.alloc_ctx);
+    else
+        (void)hipFree(p);
+}
+
 int validate(const lb_config *c)
 {
     if (!c) return LB_EINVAL;
+    if ((c->dev_alloc == nullptr) != (c->dev_free == nullptr)) return LB_EINVAL;
     if (c->lattice != LB_D3Q19 && c->lattice != LB_D2Q9) return LB_EINVAL;
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return LB_EINVAL;
     // D2Q9 is a lattice one site thick in z, stepped by the split launches
@@ -168,14 +195,14 @@ hipError_t run_collide(lb_handle *h)
                                 h->omega, h->srcfac, h->ubar, h->lm, h->matter, h->cfg.collision, h->stream);
 }
 
+// gives back every device buffer (the handle's stream must be idle)
 void free_all(lb_handle *h)
 {
-    for (int i = 0; i < 2; ++i)
-        if (h->fbuf[i]) (void)hipFree(h->fbuf[i]);
-    if (h->ubar) (void)hipFree(h->ubar);
-    if (h->ubar2) (void)hipFree(h->ubar2);
-    if (h->lm) (void)hipFree(h->lm);
-    if (h->matter_buf) (void)hipFree(h->matter_buf);
+    for (int i = 0; i < 2; ++i) dev_release(h, h->fbuf[i]);
+    dev_release(h, h->ubar);
+    dev_release(h, h->ubar2);
+    dev_release(h, h->lm);
+    dev_release(h, h->matter_buf);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
@@ -222,19 +249,17 @@ int lb_create(const lb_config *cfg, lb_handle **out)
     h->srcfac = 1.0 - 0.5 * h->omega; // (1 - dt / (2 tau))
     const Geom &G = h->G;
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc(&h->fbuf[i], dist_bytes(G, cfg->precision));
-    if (e == hipSuccess) e = hipMalloc((void **)&h->ubar, (size_t)16 * G.ps * sizeof(double));
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = dev_malloc(h, &h->fbuf[i], dist_bytes(G, cfg->precision));
+    if (e == hipSuccess) e = dev_malloc(h, (void **)&h->ubar, (size_t)16 * G.ps * sizeof(double));
     // the fused launch re-fetches the lines its 16-wide tile rows share with
     // neighbouring tiles, so the split launches are faster on large lattices:
     // AUTO selects them
     h->fused = cfg->path == LB_PATH_FUSED;
-    if (e == hipSuccess && h->fused) e = hipMalloc((void **)&h->ubar2, (size_t)16 * G.ps * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&h->lm, (size_t)7 * G.ps * sizeof(double));
+    if (e == hipSuccess && h->fused) e = dev_malloc(h, (void **)&h->ubar2, (size_t)16 * G.ps * sizeof(double));
+    if (e == hipSuccess) e = dev_malloc(h, (void **)&h->lm, (size_t)7 * G.ps * sizeof(double));
     if (e != hipSuccess) {
-        (void)hipGetLastError();
         free_all(h);
         delete h;
-        lbnr::set_last_error("hipMalloc: %s", hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE;
     }
     if (cfg->stream) {
@@ -519,13 +544,8 @@ int lb_set_matter(lb_handle *h, int kind, const double *M, int per_site, int on_
         return LB_OK;
     }
     if (!h->matter_buf) {
-        hipError_t e = hipMalloc((void **)&h->matter_buf, (size_t)10 * G.ps * sizeof(double));
-        if (e != hipSuccess) {
-            h->matter_buf = nullptr;
-            lbnr::set_last_error("hipMalloc: %s", hipGetErrorString(e));
-            (void)hipGetLastError();
-            return e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE;
-        }
+        hipError_t e = dev_malloc(h, (void **)&h->matter_buf, (size_t)10 * G.ps * sizeof(double));
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE;
     }
     // [nc][nsite] into planes of ps; ordered after the launches already queued
     LB_HIP(hipMemcpy2DAsync(h->matter_buf, G.ps * sizeof(double), M, (size_t)G.nsite * sizeof(double),

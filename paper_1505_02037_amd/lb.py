@@ -50,6 +50,11 @@ EXPORTS = (
 )
 
 
+# lb_dev_alloc_fn / lb_dev_free_fn of include/lb.h
+DEV_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+DEV_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class LBConfig(ctypes.Structure):
     _fields_ = [
         ("lattice", ctypes.c_int),
@@ -63,6 +68,9 @@ class LBConfig(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("path", ctypes.c_int),
         ("collision", ctypes.c_int),
+        ("dev_alloc", DEV_ALLOC_FN),
+        ("dev_free", DEV_FREE_FN),
+        ("alloc_ctx", ctypes.c_void_p),
     ]
 
 
@@ -140,9 +148,61 @@ def _ptr(a, nelem: int):
 
 
 def make_config(nx, ny, nz, tau, slicing=HARMONIC, precision=FP64, device=-1, stream=None,
-                path=PATH_AUTO, lattice=LB_D3Q19, collision=COLLISION_BGK) -> LBConfig:
-    return LBConfig(int(lattice), int(nx), int(ny), int(nz), float(tau), int(slicing), int(precision),
-                    int(device), ctypes.c_void_p(stream) if stream else None, int(path), int(collision))
+                path=PATH_AUTO, lattice=LB_D3Q19, collision=COLLISION_BGK, hooks=None) -> LBConfig:
+    """hooks: None, or a (DEV_ALLOC_FN, DEV_FREE_FN) pair the caller keeps alive."""
+    cfg = LBConfig(int(lattice), int(nx), int(ny), int(nz), float(tau), int(slicing), int(precision),
+                   int(device), ctypes.c_void_p(stream) if stream else None, int(path), int(collision))
+    if hooks is not None:
+        cfg.dev_alloc, cfg.dev_free = hooks
+    return cfg
+
+
+class DeviceAllocator:
+    """A device allocator for the library (the dev_alloc/dev_free hooks):
+    alloc(nbytes) returns a device address (int) or None, free(ptr) gives it
+    back.  hooks() wraps them as C callbacks, which must stay alive as long as
+    the handle (Lattice keeps them)."""
+
+    def alloc(self, nbytes: int):
+        raise NotImplementedError
+
+    def free(self, ptr: int) -> None:
+        raise NotImplementedError
+
+    def hooks(self):
+        def _alloc(nbytes, _ctx):
+            try:
+                p = self.alloc(int(nbytes))
+            except Exception:  # an exception cannot cross the C boundary: report no memory
+                return None
+            return int(p) if p else None
+
+        def _free(ptr, _ctx):
+            try:
+                self.free(int(ptr))
+            except Exception:
+                pass
+
+        return DEV_ALLOC_FN(_alloc), DEV_FREE_FN(_free)
+
+
+class TorchAllocator(DeviceAllocator):
+    """Serves the library from torch's caching allocator on `device`, so its
+    buffers count in torch.cuda.memory_allocated() and come from (and go back
+    to) torch's pool."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+
+    def alloc(self, nbytes: int):
+        import torch
+
+        return torch.cuda.caching_allocator_alloc(nbytes, device=self.device)
+
+    def free(self, ptr: int) -> None:
+        import torch
+
+        torch.cuda.caching_allocator_delete(ptr)
 
 
 def device_bytes(nx, ny, nz, tau=0.6, precision=FP64, lattice=LB_D3Q19, path=PATH_AUTO) -> int:
@@ -155,13 +215,19 @@ class Lattice:
 
     def __init__(self, nx: int, ny: int, nz: int, tau: float, slicing: int = HARMONIC,
                  precision: int = FP64, device: int = -1, stream=None, path: int = PATH_AUTO,
-                 lattice: int = LB_D3Q19, collision: int = COLLISION_BGK):
+                 lattice: int = LB_D3Q19, collision: int = COLLISION_BGK, allocator=None):
+        """allocator: None (the library's hipMalloc), "torch" (torch's caching
+        allocator on `device`) or a DeviceAllocator."""
         lib = load_library()
         self._lib = lib
         self.shape = (nz, ny, nx)
         self.nsite = nx * ny * nz
         self.nq = int(lattice)
-        cfg = make_config(nx, ny, nz, tau, slicing, precision, device, stream, path, lattice, collision)
+        if allocator == "torch":
+            allocator = TorchAllocator(device if device >= 0 else 0)
+        self._hooks = allocator.hooks() if allocator is not None else None  # alive until lb_destroy
+        cfg = make_config(nx, ny, nz, tau, slicing, precision, device, stream, path, lattice, collision,
+                          hooks=self._hooks)
         h = ctypes.c_void_p()
         _check(lib.lb_create(ctypes.byref(cfg), ctypes.byref(h)), "lb_create")
         self._h = h

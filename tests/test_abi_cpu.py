@@ -146,3 +146,43 @@ def test_build_entry_reaches_both_build_steps(monkeypatch):
     monkeypatch.setattr(oracle_build, "build", lambda verbose=False: calls.append("oracle"))
     __graft_entry__.build()
     assert calls == ["hip", "oracle"]
+
+
+def test_config_layout_matches_header(tmp_path):
+    """The binding's lb_config has the header's size and field offsets (a C
+    program built with gcc against include/lb.h prints them)."""
+    import subprocess
+
+    from paper_1505_02037_amd import lb
+
+    names = [f for f, _ in lb.LBConfig._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"lb.h\"\nint main(void) {\n"
+                   + "".join(f'  printf("%zu\\n", offsetof(lb_config, {n}));\n' for n in names)
+                   + '  printf("%zu\\n", sizeof(lb_config));\n  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert out[:-1] == [getattr(lb.LBConfig, n).offset for n in names]
+    assert out[-1] == ctypes.sizeof(lb.LBConfig)
+
+
+def test_allocator_hooks_must_come_in_pairs(lib):
+    from paper_1505_02037_amd import lb
+
+    class Never(lb.DeviceAllocator):
+        def alloc(self, nbytes):
+            return None
+
+        def free(self, ptr):
+            pass
+
+    hooks = Never().hooks()
+    cfg = lb.make_config(10, 10, 10, 0.8, hooks=hooks)
+    assert lib.lb_device_bytes(ctypes.byref(cfg)) > 0
+    cfg.dev_free = lb.DEV_FREE_FN()  # NULL
+    assert lib.lb_device_bytes(ctypes.byref(cfg)) == 0
+    cfg = lb.make_config(10, 10, 10, 0.8)
+    cfg.dev_free = hooks[1]
+    assert lib.lb_device_bytes(ctypes.byref(cfg)) == 0
+

@@ -130,3 +130,76 @@ def test_check_finite_reports_the_blow_up():
         g.step(350)
         assert not g.check_finite()
         assert not np.all(np.isfinite(g.moments()))
+
+
+class _Counting:
+    """A DeviceAllocator over torch's caching allocator that counts calls and
+    can be told to fail from its n-th allocation on."""
+
+    def __init__(self, fail_from=None):
+        from paper_1505_02037_amd import lb
+
+        base = lb.TorchAllocator(0)
+        outer = self
+
+        class A(lb.DeviceAllocator):
+            def alloc(self, nbytes):
+                if outer.fail_from is not None and outer.allocs >= outer.fail_from:
+                    return None
+                outer.allocs += 1
+                p = base.alloc(nbytes)
+                outer.live[p] = nbytes
+                return p
+
+            def free(self, ptr):
+                outer.frees += 1
+                del outer.live[ptr]
+                base.free(ptr)
+
+        self.fail_from = fail_from
+        self.allocs = self.frees = 0
+        self.live = {}
+        self.allocator = A()
+
+
+def test_torch_allocator_serves_the_handle():
+    """With the allocator hooks routed to torch's caching allocator the
+    handle's buffers count in torch's accounting, go back to it on close, and
+    the evolution is the default allocator's bit for bit."""
+    lb = _lb()
+    import torch
+
+    u0 = workloads.random_state(13, 7, 5, seed=41)
+    res = []
+    for alloc in (None, "torch"):
+        torch.cuda.synchronize()
+        before = torch.cuda.memory_allocated(0)
+        with lb.Lattice(13, 7, 5, 0.8, device=0, allocator=alloc) as g:
+            held = torch.cuda.memory_allocated(0) - before
+            if alloc == "torch":
+                assert held >= lb.device_bytes(13, 7, 5)
+            else:
+                assert held == 0
+            g.init_fields(u0)
+            g.step(6)
+            res.append((g.moments(), g.distributions()))
+        assert torch.cuda.memory_allocated(0) == before
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
+def test_allocator_failure_is_enomem_and_releases_everything():
+    lb = _lb()
+    for fail_from in (0, 1, 3):
+        c = _Counting(fail_from)
+        with pytest.raises(lb.LBError, match="out of device memory"):
+            lb.Lattice(8, 8, 8, 0.8, device=0, allocator=c.allocator)
+        assert c.allocs == fail_from and c.frees == c.allocs and not c.live
+    # per-site matter takes one more buffer from the same allocator
+    c = _Counting()
+    with lb.Lattice(6, 5, 4, 0.8, device=0, allocator=c.allocator) as g:
+        n0 = c.allocs
+        g.init_fields(workloads.minkowski(6, 5, 4))
+        g.set_matter(workloads.random_matter(6, 5, 4, seed=3))
+        g.step(2)
+        assert c.allocs == n0 + 1
+    assert c.frees == c.allocs and not c.live
