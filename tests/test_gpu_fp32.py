@@ -188,20 +188,12 @@ def test_fp32_error_norms_and_kernel_names():
 
 
 def _largest_edge(torch):
-    """Edge (256..488, step 8) of the largest cubic FP32 lattice that fits the
-    free device memory beside one 16-field FP64 moments array and a margin."""
+    """Edge (256..488) of the largest cubic FP32 lattice that fits the free
+    device memory beside one 16-field FP64 moments array and a margin."""
+    from gpu_sizing import largest_edge
     from paper_1505_02037_amd import lb
 
-    torch.cuda.empty_cache()  # memory torch cached for earlier tests counts as free here
-    free, _ = torch.cuda.mem_get_info()
-    e = 256
-    while e < 488:
-        nxt = e + 8
-        need = lb.device_bytes(nxt, nxt, nxt, precision=lb.FP32_DEV) + 16 * nxt ** 3 * 9 + (6 << 30)
-        if need > free:
-            break
-        e = nxt
-    return e
+    return largest_edge(torch, lb.FP32_DEV)
 
 
 def test_largest_fp32_lattice_rows_match_oracle():

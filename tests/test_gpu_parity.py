@@ -283,6 +283,34 @@ def test_random_state_256_cubed_sampled_sites(path, collision, slicing):
     _assert_equal(fs, fo, "distributions at sampled sites")
 
 
+def test_largest_fp64_lattice_random_state_sampled_sites():
+    """The largest cubic FP64 lattice the card holds (edge ~376), random
+    state: after two steps the moments at sampled sites (corners, faces,
+    random sites) equal the windowed oracle's bit for bit."""
+    torch = _torch()
+    import oracle_windows as ow
+    from gpu_sizing import largest_edge
+    from paper_1505_02037_amd import lb
+
+    e = largest_edge(torch, lb.FP64, lo=128, hi=512)
+    steps, tau = 2, 0.6
+    _say(f"[parity] largest FP64 lattice {e}^3 ({e ** 3 / 1e6:.0f} M sites), random state, sampled sites")
+    u0 = workloads.random_state(e, e, e, seed=376, amp=0.05)
+    cs = ow.sample_centres(e, 18, seed=377)
+    uo, _ = ow.sampled(u0, cs, tau, steps)
+    iz, iy, ix = (torch.tensor([c[k] for c in cs], device="cuda") for k in range(3))
+    with lb.Lattice(e, e, e, tau, device=0) as g:
+        g.init_fields(u0)
+        del u0
+        g.step(steps)
+        u = torch.empty((16, e, e, e), dtype=torch.float64, device="cuda")
+        g.moments(u)
+        us = u[:, iz, iy, ix].cpu().numpy()
+        del u
+    torch.cuda.empty_cache()
+    _assert_equal(us, uo, f"moments at sampled sites of {e}^3")
+
+
 def test_error_norms_small():
     torch = _torch()
     _say("[parity] error norms 9x8x7")
