@@ -64,6 +64,30 @@ def test_alone_equals_mix_bitwise(form):
     assert st["completed"] == len(REQS) and st["resident"] == 0 and st["arena_in_use"] == 0
 
 
+def test_largest_trace_request_alongside_a_small_one():
+    """The trace's largest request size (192^3, random state) resident
+    together with a small request: both equal their solo runs bit for bit
+    (the work list spans ~27600 blocks of the large request)."""
+    _need_gpu()
+    from paper_1505_02037_amd import lb, serve
+
+    print("[serve] 192^3 request beside a small one", flush=True)
+    big = workloads.random_state(192, 192, 192, seed=192, amp=0.05)
+    small = workloads.random_state(13, 7, 5, seed=193, amp=0.05)
+    ref_big = _alone(big, 0.8, 3, lb.FP64)
+    ref_small = _alone(small, 0.7, 7, lb.FP64)
+    with serve.Server(1 << 30, lb.FP64, device=0) as probe:
+        need = probe.request_bytes(192, 192, 192) + probe.request_bytes(13, 7, 5)
+    with serve.Server(need + (1 << 24), lb.FP64, max_resident=4, steps_per_launch=2, device=0) as srv:
+        ib = srv.submit(big, 0.8, 3)
+        i_s = srv.submit(small, 0.7, 7)
+        for _ in range(20):
+            if srv.advance() == 0:
+                break
+        assert np.array_equal(srv.result(ib), ref_big)
+        assert np.array_equal(srv.result(i_s), ref_small)
+
+
 def test_budget_limits_residency():
     """A budget that holds one large request at a time: requests are admitted
     as memory frees up, all finish, and the arena never exceeds the budget."""
