@@ -76,6 +76,9 @@ struct DeviceGuard {
 
 size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
 
+// padding of every (field, direction) plane, in elements (5 blocks of 64)
+constexpr size_t kPlanePad = 320;
+
 } // namespace
 
 struct lb_handle {
@@ -162,7 +165,11 @@ Geom geom_of(const lb_config *c)
     G.ny = c->ny;
     G.nz = c->nz;
     G.nsite = (uint32_t)((size_t)c->nx * c->ny * c->nz);
-    G.ps = round_up(G.nsite, 64);
+    // planes of a power-of-two size (256^3 sites: 2^27 bytes) would put a
+    // site's 19 pulls and its paired stores at power-of-two strides; an odd
+    // number of 64-element blocks of padding staggers them (the FP32 step at
+    // 256^3 ran ~3 % faster, the FP64 step unchanged)
+    G.ps = round_up(G.nsite, 64) + kPlanePad;
     G.nq = c->lattice;
     return G;
 }

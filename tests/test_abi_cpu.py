@@ -121,12 +121,12 @@ def test_device_bytes_matches_layout(lib):
     from paper_1505_02037_amd import lb
 
     n = 100 * 30 * 7
-    ps = (n + 63) // 64 * 64
+    ps = (n + 63) // 64 * 64 + 320  # planes padded by 320 elements
     assert lb.device_bytes(100, 30, 7) == (2 * 16 * 19 + 16 + 7) * ps * 8
     assert lb.device_bytes(100, 30, 7, precision=lb.FP32_DEV) == (16 * 19 + 16 + 7) * ps * 8
     assert lb.device_bytes(100, 30, 7, path=lb.PATH_FUSED) == (2 * 16 * 19 + 16 + 16 + 7) * ps * 8
     n2 = 100 * 30
-    ps2 = (n2 + 63) // 64 * 64
+    ps2 = (n2 + 63) // 64 * 64 + 320
     assert lb.device_bytes(100, 30, 1, lattice=lb.D2Q9) == (2 * 16 * 9 + 16 + 7) * ps2 * 8
     assert lb.device_bytes(100, 30, 1, precision=lb.FP32_DEV, lattice=lb.D2Q9) == (16 * 9 + 16 + 7) * ps2 * 8
 
