@@ -129,17 +129,27 @@ size_t lb_device_bytes(const lb_config *cfg);
 /* Initial distributions from the fields u0 ([16][nz][ny][nx]):
  * f_q = f^eq_q(u0) - w_q R(u0)/2 with every quantity (right-hand sides R,
  * derivatives of the lapse and metric, flux) evaluated at u0, so that the
- * half-source moments at t = 0 return u0 up to O(dt^2).  Resets the step
+ * half-source moments at t = 0 return u0 up to O(dt^2).  The paper leaves the
+ * initial distributions open; this is the equilibrium of its Eqs. alfa ..
+ * ekst shifted by the half source of its moment definition.  Resets the step
  * counter.  Synchronises the handle's stream, so u0 may be released on
  * return. */
 int lb_init_fields(lb_handle *h, const double *u0, int on_device);
 
 /* Enqueues nsteps time steps on the handle's stream; does not synchronise.
- * nsteps >= 0. */
+ * One step (Eq. numlb): pull streaming, moments with half source, the lapse
+ * and metric corrected first and differentiated (paragraph after the
+ * first-order derivative definitions), the sources (extrinsic-curvature and
+ * momentum-variable equations, Eq. Vsor) and flux, and BGK relaxation towards
+ * the equilibria with the source added (Eqs. alfa .. ekstsor).  nsteps >= 0
+ * (LB_EINVAL otherwise); LB_ESTATE before lb_init_fields or
+ * lb_set_distributions. */
 int lb_step(lb_handle *h, long long nsteps);
 
 /* Macroscopic fields u = sum_q f_q + R/2 at the current time into u_out
- * ([16][nz][ny][nx]).  Synchronises the handle's stream. */
+ * ([16][nz][ny][nx]): the moments with half the source (section "Lattice
+ * Boltzmann Model").  Synchronises the handle's stream.  LB_ESTATE before
+ * the state is set. */
 int lb_moments(lb_handle *h, double *u_out, int on_device);
 
 /* The distributions at the current time into f_out ([16][Q][nz][ny][nx],
@@ -185,7 +195,8 @@ int lb_check_finite(lb_handle *h, int *all_finite);
 int lb_set_matter(lb_handle *h, int kind, const double *M, int per_site, int on_device);
 
 /* Error norms of the current fields against u_ref ([16][nz][ny][nx]),
- * computed on the device in FP64.  Per field F (arrays of 16):
+ * computed on the device in FP64 (the error measures of section "Analysis
+ * and Simulation Errors" are formed from these).  Per field F (arrays of 16):
  *   max_abs[F] = max_x |u_F - ref_F|,  l2[F] = sqrt(sum_x (u_F - ref_F)^2 / N),
  *   ref_max[F] = max_x |ref_F|.
  * Any output pointer may be NULL.  Synchronises the handle's stream. */
@@ -208,8 +219,9 @@ int lb_set_timing(lb_handle *h, int enable);
  * entries).  Returns LB_ESTATE if no timed call has run. */
 int lb_kernel_times(lb_handle *h, const char **names, double *ms, int cap, int *count);
 
-/* Waits for the handle's stream, frees its device memory (and its stream if
- * the library created it).  NULL is ignored. */
+/* Waits for the handle's stream, frees its device memory (through the
+ * config's dev_free if it named an allocator) and its stream if the library
+ * created it.  NULL is ignored. */
 void lb_destroy(lb_handle *h);
 
 /* Static text naming an LB_* code. */
