@@ -52,10 +52,14 @@ def _code_only(text: str) -> str:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the code of the sources the timed step kernels are built from."""
+    """Hash of the code of the sources the timed step kernels are built from,
+    and of the plane padding the host sets (it moves the kernels' addresses)."""
     h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1505_02037_amd", "csrc")
     for name in STEP_SOURCES:
-        h.update(_code_only(open(os.path.join(ROOT, "paper_1505_02037_amd", "csrc", name)).read()).encode())
+        h.update(_code_only(open(os.path.join(csrc, name)).read()).encode())
+    pad = re.search(r"constexpr size_t kPlanePad = (\d+);", open(os.path.join(csrc, "lb_api.hip")).read())
+    h.update(f"plane pad {pad.group(1) if pad else 'none'}".encode())
     return h.hexdigest()[:16]
 
 

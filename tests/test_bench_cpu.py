@@ -26,6 +26,15 @@ def test_source_hash_ignores_comments_only():
     assert bench._code_only(a) != bench._code_only(c)
 
 
+def test_source_hash_covers_the_plane_padding():
+    """The padding the host gives every plane is part of the hash (it moves
+    the kernels' addresses and so their traffic)."""
+    import re
+
+    src = open(os.path.join(ROOT, "paper_1505_02037_amd", "csrc", "lb_api.hip")).read()
+    assert re.search(r"constexpr size_t kPlanePad = \d+;", src)
+
+
 def test_traffic_summary_is_used_only_for_matching_sources():
     path = os.path.join(ROOT, "profiles", "traffic_fp64_step.json")
     d = json.load(open(path))
