@@ -223,7 +223,9 @@ def main() -> int:
     step_kernel_ms = sum(ktimes.values())
     alg_bytes = ALG_BYTES_PER_SITE[args.form] * nsite
     achieved = alg_bytes / (step_kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(nsite, args.form) if (args.path, args.collision) == ("split", "bgk") else None
+    # the counters were taken on the default launch at 256^3
+    traffic = (measured_traffic(nsite, args.form)
+               if (args.path, args.collision, n) == ("split", "bgk", 256) else None)
     line = {
         "metric": "field-site updates/s",
         "value": value,
