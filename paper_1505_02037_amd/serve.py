@@ -15,7 +15,6 @@ from __future__ import annotations
 import argparse
 import ctypes
 import json
-import math
 import sys
 import time
 
